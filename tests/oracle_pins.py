@@ -1,0 +1,233 @@
+"""Pins for the FP64 oracle: checks that tie it to something other than itself.
+
+Each pin takes a convolution callable ``conv(A, k) -> B`` (A is [P, R, C]
+float64, k holds 5 taps) so the same pins can be run against deliberately
+broken copies of the oracle (see test_oracle_mutants.py) and must reject them.
+
+Sources of truth used here, none of which is the oracle:
+* library routines: scipy.signal.correlate2d and torch conv2d (CPU, float64),
+  which compute Eq. 1 as a correlation on the 'valid' region;
+* brute force: Eq. 1 written with an explicit K[i][j] = k_i k_j matrix in
+  pure Python on tiny images;
+* closed forms: delta impulse, constant image, linear ramp, exact rationals.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+
+def _interior_expected(A: np.ndarray, K: np.ndarray, valid) -> np.ndarray:
+    P, R, C = A.shape
+    B = np.zeros_like(A)
+    if R >= 5 and C >= 5:
+        for p in range(P):
+            B[p, 2:R - 2, 2:C - 2] = valid(A[p], K)
+    return B
+
+
+def pin_scipy(conv) -> bool:
+    """Eq. 1 as scipy's 2-D correlation on the 'valid' region, border 0."""
+    from scipy.signal import correlate2d
+
+    rng = np.random.default_rng(11)
+    for (P, R, C) in ((3, 17, 23), (2, 40, 9), (1, 5, 5), (3, 64, 67)):
+        A = rng.random((P, R, C)) * 2 - 1
+        k = rng.random(5) * 2 - 1
+        K = np.outer(k, k)
+        ref = _interior_expected(A, K, lambda a, K: correlate2d(a, K, mode="valid"))
+        got = conv(A, k)
+        if got.shape != ref.shape or not np.allclose(got, ref, rtol=0, atol=1e-13):
+            return False
+    return True
+
+
+def pin_torch(conv) -> bool:
+    """Eq. 1 as torch's conv2d (a cross-correlation) in float64 on the CPU."""
+    import torch
+
+    rng = np.random.default_rng(12)
+    A = rng.random((3, 33, 29)) * 2 - 1
+    k = rng.random(5) * 2 - 1
+    K = torch.from_numpy(np.outer(k, k))[None, None]
+    t = torch.from_numpy(A)[:, None]
+    valid = torch.nn.functional.conv2d(t, K)[:, 0].numpy()
+    ref = np.zeros_like(A)
+    ref[:, 2:-2, 2:-2] = valid
+    got = conv(A, k)
+    return bool(np.allclose(got, ref, rtol=0, atol=1e-13))
+
+
+def _brute(a2d, k):
+    R, C = len(a2d), len(a2d[0])
+    K = [[k[i] * k[j] for j in range(5)] for i in range(5)]
+    out = [[0.0] * C for _ in range(R)]
+    for y in range(2, R - 2):
+        for x in range(2, C - 2):
+            s = 0.0
+            for i in range(5):
+                for j in range(5):
+                    s += a2d[y + i - 2][x + j - 2] * K[i][j]
+            out[y][x] = s
+    return out
+
+
+def pin_bruteforce_tiny(conv) -> bool:
+    """Every H, W in 1..12 (H or W < 5 gives an all-zero result)."""
+    rng = np.random.default_rng(13)
+    k = rng.random(5) * 2 - 1
+    for R in range(1, 13):
+        for C in range(1, 13):
+            A = rng.random((1, R, C)) * 2 - 1
+            ref = np.array(_brute(A[0].tolist(), k.tolist()))
+            got = conv(A, k)
+            if got.shape != (1, R, C) or not np.allclose(got[0], ref, rtol=0, atol=1e-14):
+                return False
+    return True
+
+
+def pin_delta(conv) -> bool:
+    """A unit impulse at (y0, x0) gives B[y0+d][x0+e] = k[2-d] k[2-e]."""
+    k = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
+    R, C, y0, x0 = 13, 15, 6, 7
+    A = np.zeros((1, R, C))
+    A[0, y0, x0] = 1.0
+    ref = np.zeros((R, C))
+    for d in range(-2, 3):
+        for e in range(-2, 3):
+            ref[y0 + d, x0 + e] = k[2 - d] * k[2 - e]
+    got = conv(A, k)[0]
+    return bool(np.array_equal(got, ref))
+
+
+def pin_constant(conv) -> bool:
+    """A constant image c gives c (sum k)^2 on the interior and 0 outside."""
+    k = np.array([0.5, -0.25, 1.0, 0.125, 0.75])
+    c = 3.0
+    A = np.full((2, 9, 11), c)
+    got = conv(A, k)
+    ref = np.zeros_like(A)
+    ref[:, 2:-2, 2:-2] = c * k.sum() ** 2
+    return bool(np.allclose(got, ref, rtol=1e-15, atol=0))
+
+
+def pin_ramp(conv) -> bool:
+    """A = a + b y + c x with asymmetric taps (closed form, pins orientation).
+
+    B = S^2 (a + b y + c x) + S m (b + c) with S = sum k and
+    m = sum_j j k[j + 2] (first moment); a flipped (convolution-form) kernel
+    would flip the sign of m.
+    """
+    k = np.array([0.05, 0.1, 0.15, 0.3, 0.4])
+    a, b, c = 0.5, 2.0, -3.0
+    R, C = 12, 14
+    yy, xx = np.meshgrid(np.arange(R), np.arange(C), indexing="ij")
+    A = (a + b * yy + c * xx)[None].astype(np.float64)
+    S = k.sum()
+    m = float(np.dot(np.arange(-2, 3), k))
+    ref = np.zeros_like(A)
+    ref[0, 2:-2, 2:-2] = (S * S * (a + b * yy + c * xx) + S * m * (b + c))[2:-2, 2:-2]
+    got = conv(A, k)
+    return bool(np.allclose(got, ref, rtol=1e-13, atol=1e-13))
+
+
+def pin_exact_rational(conv) -> bool:
+    """m/256 pixels, binomial taps: every term is exact; compare with Fractions."""
+    rng = np.random.default_rng(14)
+    M = rng.integers(0, 256, size=(2, 9, 10))
+    A = M / 256.0
+    kf = [Fraction(v, 16) for v in (1, 4, 6, 4, 1)]
+    k = np.array([float(v) for v in kf])
+    got = conv(A, k)
+    for p in range(2):
+        for y in range(9):
+            for x in range(10):
+                if 2 <= y < 7 and 2 <= x < 8:
+                    s = sum(Fraction(int(M[p, y + i - 2, x + j - 2]), 256) * kf[i] * kf[j]
+                            for i in range(5) for j in range(5))
+                else:
+                    s = Fraction(0)
+                if Fraction(float(got[p, y, x])) != s:
+                    return False
+    return True
+
+
+def pin_planes_independent(conv) -> bool:
+    """Each plane is convolved on its own (plane permutation commutes)."""
+    rng = np.random.default_rng(15)
+    A = rng.random((3, 10, 12))
+    k = rng.random(5)
+    B = conv(A, k)
+    Bp = conv(A[[2, 0, 1]], k)
+    single = [conv(A[p:p + 1], k)[0] for p in range(3)]
+    return bool(np.array_equal(Bp, B[[2, 0, 1]])
+                and all(np.array_equal(single[p], B[p]) for p in range(3)))
+
+
+def pin_transpose(conv) -> bool:
+    """K = k k^T is symmetric, so conv(A^T) = conv(A)^T."""
+    rng = np.random.default_rng(16)
+    A = rng.random((1, 11, 16))
+    k = rng.random(5) * 2 - 1
+    B = conv(A, k)[0]
+    Bt = conv(np.ascontiguousarray(A[0].T)[None], k)[0]
+    return bool(np.allclose(Bt, B.T, rtol=0, atol=1e-14))
+
+
+def pin_linear(conv) -> bool:
+    """conv(alpha A1 + beta A2) = alpha conv(A1) + beta conv(A2)."""
+    rng = np.random.default_rng(17)
+    A1, A2 = rng.random((2, 1, 12, 13))
+    k = rng.random(5)
+    lhs = conv(2.0 * A1 - 0.5 * A2, k)
+    rhs = 2.0 * conv(A1, k) - 0.5 * conv(A2, k)
+    return bool(np.allclose(lhs, rhs, rtol=0, atol=1e-13))
+
+
+CONV_PINS = {
+    "scipy": pin_scipy,
+    "torch": pin_torch,
+    "bruteforce_tiny": pin_bruteforce_tiny,
+    "delta": pin_delta,
+    "constant": pin_constant,
+    "ramp": pin_ramp,
+    "exact_rational": pin_exact_rational,
+    "planes_independent": pin_planes_independent,
+    "transpose": pin_transpose,
+    "linear": pin_linear,
+}
+
+
+def failing_pins(conv) -> list[str]:
+    bad = []
+    for name, pin in CONV_PINS.items():
+        try:
+            ok = pin(conv)
+        except Exception:
+            ok = False
+        if not ok:
+            bad.append(name)
+    return bad
+
+
+# ---- rounding / decoding pins -------------------------------------------
+
+def _bf16_table():
+    bits = np.arange(1 << 16, dtype=np.uint32)
+    vals = (bits << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    return bits.astype(np.uint16), vals
+
+
+def nearest_even_bf16(x: float) -> int:
+    """Brute force: the bf16 pattern nearest to the finite double x, compared
+    with exact rationals; ties go to the even pattern (fraction LSB 0)."""
+    bits, vals = _bf16_table()
+    same = (np.signbit(vals) == np.signbit(x)) & np.isfinite(vals)
+    cand = np.where(same)[0]
+    v = vals[cand]
+    order = np.argsort(np.abs(v - x), kind="stable")[:4]
+    fx = Fraction(x)
+    best = min(order, key=lambda i: (abs(Fraction(float(v[i])) - fx),
+                                     int(bits[cand[i]]) & 1))
+    return int(bits[cand[best]])

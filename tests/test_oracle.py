@@ -1,0 +1,144 @@
+"""The FP64 oracle against what the paper and the mathematics fix (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import oracle_pins as pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.txt")
+
+
+@pytest.mark.parametrize("name", sorted(pins.CONV_PINS))
+def test_direct_pins(name):
+    assert pins.CONV_PINS[name](oracle.conv5), name
+
+
+@pytest.mark.parametrize("name", ["scipy", "delta", "constant", "ramp",
+                                  "exact_rational", "bruteforce_tiny"])
+def test_twopass_pins(name):
+    assert pins.CONV_PINS[name](oracle.conv5_twopass), name
+
+
+def test_separability_fp64():
+    """Two-pass FP64 == single-pass FP64 (Eq. 1 with K = k k^T) to rounding."""
+    rng = np.random.default_rng(21)
+    for shape in ((3, 64, 80), (1, 5, 5), (2, 7, 33)):
+        A = rng.random(shape)
+        k = rng.random(5) * 2 - 1
+        d = oracle.conv5(A, k)
+        t = oracle.conv5_twopass(A, k)
+        scale = np.abs(A).max() * np.abs(k).sum() ** 2
+        assert np.max(np.abs(d - t)) <= 1e-15 * 25 * scale
+
+
+def _read_golden():
+    cases, lines = [], [ln.strip() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
+    i = 0
+    while i < len(lines):
+        _, name, r, c = lines[i].split()
+        r, c = int(r), int(c)
+        k = [float(v) for v in lines[i + 1].split()[1:]]
+        A = np.array([[float(v) for v in lines[i + 2 + y].split()] for y in range(r)])
+        assert lines[i + 2 + r] == "expect"
+        E = np.array([[float(v) for v in lines[i + 3 + r + y].split()] for y in range(r)])
+        cases.append((name, A, k, E))
+        i += 3 + 2 * r
+    return cases
+
+
+def test_golden_worked_examples():
+    cases = _read_golden()
+    assert {c[0] for c in cases} == {"single_pixel", "impulse", "too_small"}
+    for name, A, k, E in cases:
+        assert np.array_equal(oracle.conv5(A, k), E), name
+        assert np.array_equal(oracle.conv5_twopass(A, k), E), name
+
+
+def test_border_zero_and_tiny():
+    rng = np.random.default_rng(22)
+    A = rng.random((3, 20, 30)) + 1.0
+    B = oracle.conv5(A, rng.random(5) + 0.1)
+    assert np.all(B[:, :2, :] == 0) and np.all(B[:, -2:, :] == 0)
+    assert np.all(B[:, :, :2] == 0) and np.all(B[:, :, -2:] == 0)
+    assert np.all(B[:, 2:-2, 2:-2] > 0)
+    for shape in ((3, 4, 100), (3, 100, 4), (1, 1, 1), (2, 0, 7), (0, 5, 5)):
+        A = rng.random(shape)
+        B = oracle.conv5(A, [1, 2, 3, 4, 5])
+        assert B.shape == A.shape and not np.any(B)
+
+
+def test_threads_do_not_change_result():
+    rng = np.random.default_rng(23)
+    A = rng.random((3, 50, 61))
+    k = rng.random(5)
+    assert np.array_equal(oracle.conv5(A, k, nthreads=1), oracle.conv5(A, k, nthreads=4))
+
+
+# ---- storage decoding and rounding ---------------------------------------
+
+def test_decode_f16_all_patterns():
+    bits = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    got = oracle.decode(bits, "f16")
+    ref = bits.view(np.float16).astype(np.float64)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan], ref[~nan])
+    assert np.array_equal(np.signbit(got[~nan]), np.signbit(ref[~nan]))
+
+
+def test_decode_bf16_all_patterns():
+    bits = np.arange(1 << 16, dtype=np.uint32)
+    got = oracle.decode(bits.astype(np.uint16), "bf16")
+    ref = (bits << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan], ref[~nan])
+
+
+def _rounding_probe_values(rng, lo_exp, hi_exp, n):
+    mant = rng.random(n) + 1.0
+    ex = rng.integers(lo_exp, hi_exp, size=n)
+    v = np.ldexp(mant, ex) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    return v
+
+
+def test_round_f16_matches_numpy():
+    """numpy's binary64 -> binary16 cast rounds once to nearest even."""
+    rng = np.random.default_rng(24)
+    v = _rounding_probe_values(rng, -30, 17, 200000)
+    # exact midpoints between neighbouring halves, and points just off them
+    h = rng.integers(0, 0x7bff, size=20000).astype(np.uint16)
+    a = h.view(np.float16).astype(np.float64)
+    b = (h + 1).astype(np.uint16).view(np.float16).astype(np.float64)
+    mid = (a + b) / 2
+    v = np.concatenate([v, mid, np.nextafter(mid, 0), np.nextafter(mid, np.inf),
+                        [0.0, -0.0, 65504.0, 65519.99, 65520.0, 1e9, -1e9, 2.0 ** -25,
+                         2.0 ** -25 * 1.0000001, 2.0 ** -26]])
+    got = oracle.round_to(v, "f16")
+    ref = v.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got, ref)
+
+
+def test_round_bf16_matches_bruteforce():
+    """Nearest bf16 by exhaustive search with exact rationals, ties to even."""
+    rng = np.random.default_rng(25)
+    bits = rng.integers(0, 0x7f7f, size=60).astype(np.uint32)
+    lo = (bits << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    hi = ((bits + 1) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    mid = (lo + hi) / 2
+    vals = np.concatenate([mid, np.nextafter(mid, 0), np.nextafter(mid, np.inf),
+                           _rounding_probe_values(rng, -140, 120, 60),
+                           [2.0 ** -134, 3 * 2.0 ** -135, 2.0 ** -135, 1.0, 1.00390625]])
+    got = oracle.round_to(vals, "bf16")
+    for v, g in zip(vals, got):
+        assert int(g) == pins.nearest_even_bf16(float(v)), v
+
+
+def test_round_bf16_overflow_and_specials():
+    big = float(np.float32(3.3895314e38))  # largest finite bf16
+    got = oracle.round_to(np.array([big, 3.4e38, -3.4e38, np.inf, np.nan, 0.0, -0.0]), "bf16")
+    assert list(got[:4]) == [0x7f7f, 0x7f80, 0xff80, 0x7f80]
+    assert (int(got[4]) & 0x7f80) == 0x7f80 and (int(got[4]) & 0x7f)
+    assert list(got[5:]) == [0x0000, 0x8000]
