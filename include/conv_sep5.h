@@ -1,0 +1,259 @@
+/*
+ * conv_sep5.h -- C ABI of the width-5 separable image convolution library
+ * (libconvsep5.so) for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (arXiv 1711.09791, Section 1, Eq. 1 with the separable kernel
+ * K[i][j] = k_i k_j defined right after it):
+ *
+ *     B[p][y][x] = sum_{i=-2..2} sum_{j=-2..2} A[p][y+i][x+j] * k[i+2] * k[j+2]
+ *
+ * for every plane p and every pixel whose 5x5 neighbourhood lies inside the
+ * image (2 <= y < rows-2, 2 <= x < cols-2; Section 4 starts the convolution at
+ * pixel (2,2) and ignores the edges).  Every other output pixel (the 2-pixel
+ * frame) is written as +0.0.  The form is a correlation: k[0] weights the
+ * neighbour at offset -2 (the tap order of the paper's listings in
+ * Sections 4.3 and 4.4).  Images smaller than 5 in either dimension have no
+ * interior and come out all zeros.
+ *
+ * Arithmetic: FP32 accumulation in every storage type.  The horizontal and the
+ * vertical 5-tap filters are each one multiply followed by four fused
+ * multiply-adds in tap order k[0]..k[4].  The two-pass and the fused one-pass
+ * forms perform the same operations on the same values, so their outputs are
+ * bitwise identical; so are the batched, graph-replayed and served results
+ * for the same image and taps.  The direct 25-tap mode (the paper's
+ * single-pass arithmetic, Section 4.1, Eq. 2 / Eq. 3) rounds K[a][b] once
+ * to FP32 on the host, runs a 5-term FMA chain per kernel row and adds the
+ * five row partials pairwise.
+ *
+ * Conventions shared by every entry point:
+ *  - Device pointers are plain HIP device addresses (for example the data
+ *    pointer of a torch tensor); the caller owns them and keeps them alive
+ *    until the stream work completes (or, for the server, until poll reports
+ *    the ticket done).  Host arrays (taps, descriptors) are copied before the
+ *    call returns.
+ *  - Calls only enqueue work on the given stream (NULL = the default stream of
+ *    the current device); nothing synchronises except conv_serve_destroy and
+ *    the tuner.  All work runs on the device current at call time.
+ *  - Arguments are validated before any HIP call.  Errors are returned as a
+ *    conv_status; a thread-local message is available from conv_last_error().
+ *    No C++ exception crosses this boundary.
+ */
+#ifndef CONV_SEP5_H
+#define CONV_SEP5_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CONV_OK = 0,
+    CONV_EINVAL = -1,    /* bad argument (null pointer, bad shape, dtype, mode) */
+    CONV_EALIAS = -2,    /* input and output (or workspace) byte ranges overlap */
+    CONV_ENOMEM = -3,    /* allocation failed / request larger than a budget   */
+    CONV_EHIP = -4,      /* a HIP runtime call or kernel launch failed          */
+    CONV_EAGAIN = -5,    /* serving: the ticket is still pending                */
+    CONV_ENOTFOUND = -6  /* serving: unknown (or already reported) ticket       */
+} conv_status;
+
+/* Storage type of the input and output image.  Accumulation is FP32 always. */
+typedef enum { CONV_F32 = 0, CONV_F16 = 1, CONV_BF16 = 2 } conv_dtype;
+
+/*
+ * Image descriptor (the paper's planes/rows/cols image record, Section 4.3,
+ * with planar [plane][row][col] storage, Section 4.1 Eq. 2, and the flat
+ * index p*rows*cols + r*cols + c of Section 4.4 generalised by strides).
+ * Element (p, y, x) lives at base + p*plane_stride + y*pitch + x, counted in
+ * elements of `dtype`.  The same layout applies to the input and the output.
+ *   planes       >= 0 (3 colour planes in the paper's workload)
+ *   rows, cols   >= 0 (any of planes/rows/cols == 0 means "nothing to do")
+ *   pitch        elements between rows; 0 means cols; otherwise >= cols
+ *   plane_stride elements between planes; 0 means rows*pitch; otherwise
+ *                >= (rows-1)*pitch + cols
+ * The fast path needs 16-byte aligned base pointers and cols, pitch and
+ * plane_stride that are multiples of 16/sizeof(element); other layouts run a
+ * slower element-wise path with identical results.
+ */
+typedef struct {
+    int32_t planes;
+    int32_t rows;
+    int32_t cols;
+    int32_t dtype;        /* conv_dtype */
+    int64_t pitch;
+    int64_t plane_stride;
+} conv_image;
+
+/* conv_sep5_1pass modes. */
+enum {
+    CONV_1PASS_FUSED = 0,    /* row-filtered intermediate kept in registers */
+    CONV_1PASS_DIRECT25 = 1  /* 25 multiply-adds per pixel (Eq. 2 / Eq. 3)  */
+};
+
+/*
+ * Two-pass form (Section 4.1, "two-pass algorithm"; Section 4.3 and 4.4
+ * listings): a row kernel filters every row of every plane horizontally into
+ * the FP32 workspace `d_tmp`, then a column kernel filters it vertically into
+ * `d_out`.  The two kernels are ordered on `stream` (the analogue of the
+ * barrier between the passes).
+ *   d_in, d_out  device images described by *img; d_out == d_in is allowed
+ *                (the paper's in-place two-pass, Section 6) -- any other
+ *                partial overlap is CONV_EALIAS.
+ *   d_tmp        FP32 workspace of planes*rows*cols floats, dense
+ *                [plane][row][col]; must not overlap d_in or d_out.  NULL
+ *                makes the library take stream-ordered memory for it
+ *                (hipMallocAsync / hipFreeAsync on `stream`).
+ *   k            5 FP32 taps (host array).
+ */
+conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp,
+                            const float k[5], const conv_image *img,
+                            hipStream_t stream);
+
+/*
+ * Single-pass form (Section 4.1 and Section 6, "single-pass without
+ * copy-back": the result is written once to a separate output).  One kernel;
+ * mode CONV_1PASS_FUSED keeps the row-filtered rows in registers, mode
+ * CONV_1PASS_DIRECT25 evaluates the 25-term sum of Eq. 2.
+ *   d_in, d_out  device images described by *img; must not overlap
+ *                (CONV_EALIAS).
+ *   k            5 FP32 taps (host array).
+ */
+conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
+                            const conv_image *img, int mode,
+                            hipStream_t stream);
+
+/*
+ * Many images of different sizes in ONE persistent kernel launch (the
+ * device-side counterpart of the paper's task agglomeration over planes,
+ * Section 5).  All images must share one dtype; each has its own taps.
+ *   n            number of images (>= 0; 0 enqueues nothing)
+ *   d_in, d_out  host arrays of n device pointers
+ *   k            host array of n*5 FP32 taps (image i uses k[5i .. 5i+4])
+ *   imgs         host array of n descriptors
+ *   mode         CONV_1PASS_FUSED or CONV_1PASS_DIRECT25
+ * Each output must not overlap its own input or any other image's output.
+ * The per-launch descriptor table is staged through a library-owned pinned
+ * ring and copied to device memory on `stream`.
+ */
+conv_status conv_sep5_batch(int32_t n, const void *const *d_in,
+                            void *const *d_out, const float *k,
+                            const conv_image *imgs, int mode,
+                            hipStream_t stream);
+
+/*
+ * A batch bound once to fixed buffers and replayed as a captured hipGraph.
+ * plan_create validates like conv_sep5_batch, uploads the descriptor table to
+ * library-owned device memory and captures the launch; plan_launch replays
+ * the graph on `stream`; plan_destroy frees the plan (the caller must make
+ * sure no replay is still running).
+ */
+typedef struct conv_plan conv_plan;
+conv_status conv_batch_plan_create(int32_t n, const void *const *d_in,
+                                   void *const *d_out, const float *k,
+                                   const conv_image *imgs, int mode,
+                                   conv_plan **plan);
+conv_status conv_batch_plan_launch(conv_plan *plan, hipStream_t stream);
+conv_status conv_batch_plan_destroy(conv_plan *plan);
+
+/*
+ * Tile configuration (the autotuner's search space).  Results never depend on
+ * it: every configuration gives bitwise identical output.
+ *   rows_per_tile  output rows a wavefront walks down per tile (4..4096)
+ *   waves_per_wg   wavefronts per workgroup, each on its own column strip
+ *                  (1, 2 or 4)
+ *   persist_wgs_per_cu  batch kernel: resident workgroups per compute unit
+ *                  (1..32); the persistent grid is this times the CU count
+ */
+typedef struct {
+    int32_t rows_per_tile;
+    int32_t waves_per_wg;
+    int32_t persist_wgs_per_cu;
+} conv_tile_cfg;
+
+/* kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel. */
+conv_status conv_get_tile_cfg(int32_t dtype, int32_t kind, conv_tile_cfg *cfg);
+conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *cfg);
+
+/*
+ * Autotuner: times every candidate configuration of `kind` on the given
+ * workload with HIP events (`reps` timed launches each, after one warm-up),
+ * installs the fastest with conv_set_tile_cfg and returns it in *best, with
+ * its median time per launch in *best_ms.  kind 0 tunes on image 0 alone
+ * (fused 1pass), kind 1 on the whole batch.  Synchronises `stream`.
+ */
+conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_in,
+                      void *const *d_out, const float *k,
+                      const conv_image *imgs, int32_t reps,
+                      hipStream_t stream, conv_tile_cfg *best, float *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching server.  A scheduler thread admits submitted requests in
+ * arrival order while a slot is free and their HBM footprint (input + output
+ * bytes) fits the budget, packs every admitted request into one persistent
+ * batch launch on the next idle stream, and retires requests when the launch's
+ * event completes.  Requests that arrive while others run are admitted into
+ * the next launch, on another stream, so their work overlaps on the device.
+ * Each result is bitwise identical to a lone conv_sep5_1pass (fused) call.
+ */
+typedef struct {
+    uint64_t hbm_budget_bytes; /* max sum of footprints in flight (> 0)      */
+    int32_t max_slots;         /* max requests in flight (>= 1)              */
+    int32_t n_streams;         /* launch streams (1..16)                     */
+    int32_t max_batch;         /* max requests per launch (>= 1)             */
+    int32_t device;            /* HIP device ordinal (-1: current device)    */
+} conv_serve_cfg;
+
+typedef struct {
+    uint64_t submit_ns;  /* host CLOCK_MONOTONIC at submit                    */
+    uint64_t admit_ns;   /* when the scheduler admitted it into a launch      */
+    uint64_t launch_ns;  /* when that launch was enqueued                     */
+    uint64_t done_ns;    /* when the scheduler saw the launch's event done    */
+    int32_t batch_size;  /* requests in its launch                            */
+    int32_t stream;      /* index of the stream it ran on                     */
+} conv_req_times;
+
+typedef struct conv_server conv_server;
+
+conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv);
+/* Non-blocking.  d_in/d_out: device image (FP32/FP16/BF16) as in
+ * conv_sep5_1pass; k: 5 host taps.  Footprint larger than the budget ->
+ * CONV_ENOMEM; bad arguments -> CONV_EINVAL / CONV_EALIAS.  *ticket > 0. */
+conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out,
+                              const float k[5], const conv_image *img,
+                              uint64_t *ticket);
+/* CONV_OK: done (times filled if t != NULL; the ticket is then forgotten);
+ * CONV_EAGAIN: pending; CONV_ENOTFOUND: unknown ticket; CONV_EHIP: its launch
+ * failed. */
+conv_status conv_serve_poll(conv_server *srv, uint64_t ticket,
+                            conv_req_times *t);
+/* Blocks until every submitted request has completed. */
+conv_status conv_serve_drain(conv_server *srv);
+
+/* Counters since creation (for tests and benchmarks). */
+typedef struct {
+    uint64_t submitted;           /* accepted submissions                     */
+    uint64_t completed;           /* requests whose launch finished           */
+    uint64_t failed;              /* requests whose launch failed             */
+    uint64_t launches;            /* batch launches enqueued                  */
+    uint64_t max_bytes_in_flight; /* high-water mark of admitted footprints   */
+    int32_t max_slots_in_flight;  /* high-water mark of admitted requests     */
+    int32_t max_batch;            /* largest launch                           */
+    int32_t max_streams_busy;     /* most launches in flight at once          */
+    int32_t reserved;
+} conv_serve_stats;
+conv_status conv_serve_get_stats(conv_server *srv, conv_serve_stats *stats);
+/* Drains, stops the scheduler and frees the server. */
+conv_status conv_serve_destroy(conv_server *srv);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char *conv_last_error(void);
+
+/* Library version string. */
+const char *conv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONV_SEP5_H */

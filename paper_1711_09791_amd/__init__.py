@@ -1,0 +1,363 @@
+"""Width-5 separable image convolution on AMD Instinct MI355X (gfx950).
+
+A thin ctypes binding over ``libconvsep5.so`` (C ABI in ``include/conv_sep5.h``).
+The functions carry the C names and only marshal arguments: every step of the
+convolution runs in the library's HIP kernels.  torch tensors supply device
+memory and streams.  If the library is not built, every call raises.
+
+Image tensors are [planes, rows, cols] (float32, float16 or bfloat16) on the
+GPU with unit column stride; row and plane strides become the descriptor's
+pitch and plane_stride.  Taps are 5 FP32 numbers; k[0] weights the neighbour at
+offset -2 (correlation form of Eq. 1, arXiv 1711.09791).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libconvsep5.so")
+
+CONV_OK, CONV_EINVAL, CONV_EALIAS, CONV_ENOMEM = 0, -1, -2, -3
+CONV_EHIP, CONV_EAGAIN, CONV_ENOTFOUND = -4, -5, -6
+CONV_F32, CONV_F16, CONV_BF16 = 0, 1, 2
+CONV_1PASS_FUSED, CONV_1PASS_DIRECT25 = 0, 1
+KIND_IMAGE, KIND_BATCH = 0, 1
+
+_STATUS_NAMES = {0: "CONV_OK", -1: "CONV_EINVAL", -2: "CONV_EALIAS", -3: "CONV_ENOMEM",
+                 -4: "CONV_EHIP", -5: "CONV_EAGAIN", -6: "CONV_ENOTFOUND"}
+
+
+class conv_image(ctypes.Structure):
+    _fields_ = [("planes", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("pitch", ctypes.c_int64), ("plane_stride", ctypes.c_int64)]
+
+
+class conv_tile_cfg(ctypes.Structure):
+    _fields_ = [("rows_per_tile", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
+                ("persist_wgs_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class conv_serve_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class conv_req_times(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("launch_ns", ctypes.c_uint64), ("done_ns", ctypes.c_uint64),
+                ("batch_size", ctypes.c_int32), ("stream", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class conv_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("max_bytes_in_flight", ctypes.c_uint64), ("max_slots_in_flight", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_streams_busy", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
+class ConvError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = (
+    "conv_sep5_2pass", "conv_sep5_1pass", "conv_sep5_batch",
+    "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
+    "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_tune",
+    "conv_serve_create", "conv_serve_submit", "conv_serve_poll", "conv_serve_drain",
+    "conv_serve_destroy", "conv_serve_get_stats", "conv_last_error", "conv_version",
+)
+
+
+def lib():
+    """The loaded libconvsep5.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"libconvsep5.so is not built ({LIB_PATH}); run `python -m "
+            "paper_1711_09791_amd.build` or __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    fp = ctypes.POINTER(ctypes.c_float)
+    imgp = ctypes.POINTER(conv_image)
+    cfgp = ctypes.POINTER(conv_tile_cfg)
+    sig = {
+        "conv_sep5_2pass": [vp, vp, vp, fp, imgp, vp],
+        "conv_sep5_1pass": [vp, vp, fp, imgp, ctypes.c_int, vp],
+        "conv_sep5_batch": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, ctypes.c_int, vp],
+        "conv_batch_plan_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp,
+                                   ctypes.c_int, ctypes.POINTER(vp)],
+        "conv_batch_plan_launch": [vp, vp],
+        "conv_batch_plan_destroy": [vp],
+        "conv_get_tile_cfg": [i32, i32, cfgp],
+        "conv_set_tile_cfg": [i32, i32, cfgp],
+        "conv_tune": [i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, i32, vp, cfgp,
+                      fp],
+        "conv_serve_create": [ctypes.POINTER(conv_serve_cfg), ctypes.POINTER(vp)],
+        "conv_serve_submit": [vp, vp, vp, fp, imgp, ctypes.POINTER(u64)],
+        "conv_serve_poll": [vp, u64, ctypes.POINTER(conv_req_times)],
+        "conv_serve_drain": [vp],
+        "conv_serve_destroy": [vp],
+        "conv_serve_get_stats": [vp, ctypes.POINTER(conv_serve_stats)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.conv_last_error.argtypes = []
+    L.conv_last_error.restype = ctypes.c_char_p
+    L.conv_version.argtypes = []
+    L.conv_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def conv_last_error() -> str:
+    return lib().conv_last_error().decode()
+
+
+def _check(st: int) -> int:
+    if st != CONV_OK:
+        raise ConvError(st, conv_last_error())
+    return st
+
+
+# ---- argument marshalling ------------------------------------------------------------
+
+def _dtype_code(t) -> int:
+    import torch
+
+    m = {torch.float32: CONV_F32, torch.float16: CONV_F16, torch.bfloat16: CONV_BF16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def image_of(t) -> conv_image:
+    """conv_image describing a [planes, rows, cols] (or [rows, cols]) tensor."""
+    if t.dim() in (2, 3) and t.numel() == 0:
+        shape = (1, *t.shape) if t.dim() == 2 else tuple(t.shape)
+        return conv_image(*(int(v) for v in shape), _dtype_code(t), 0, 0)
+    if t.dim() == 2:
+        P, (R, C) = 1, t.shape
+        sp, sr, sc = R * t.stride(0), t.stride(0), t.stride(1)
+    elif t.dim() == 3:
+        P, R, C = t.shape
+        sp, sr, sc = t.stride()
+    else:
+        raise ValueError("image tensors are [planes, rows, cols] or [rows, cols]")
+    if C > 1 and sc != 1:
+        raise ValueError("columns must be contiguous (unit stride)")
+    return conv_image(int(P), int(R), int(C), _dtype_code(t), int(sr) if R > 1 else int(C),
+                      int(sp) if P > 1 else 0)
+
+
+def _taps(k) -> ctypes.Array:
+    vals = [float(v) for v in (k.tolist() if hasattr(k, "tolist") else k)]
+    if len(vals) != 5:
+        raise ValueError("k must hold 5 taps")
+    return (ctypes.c_float * 5)(*vals)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(x):
+    if x is None:
+        return ctypes.c_void_p(0)
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+# ---- entry points ----------------------------------------------------------------------
+
+def conv_sep5_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, stream=None):
+    """Two-pass form: row kernel into the FP32 workspace, then column kernel."""
+    img = img or image_of(d_in)
+    return _check(lib().conv_sep5_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
+                                        ctypes.byref(img), _stream(stream)))
+
+
+def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
+                    img: conv_image | None = None, stream=None):
+    """Single-pass form (fused row+column, or the direct 25-tap mode)."""
+    img = img or image_of(d_in)
+    return _check(lib().conv_sep5_1pass(_ptr(d_in), _ptr(d_out), _taps(k), ctypes.byref(img),
+                                        int(mode), _stream(stream)))
+
+
+def _batch_args(ins, outs, ks, imgs):
+    n = len(ins)
+    if len(outs) != n or len(ks) != n:
+        raise ValueError("ins, outs and ks must have the same length")
+    imgs = list(imgs) if imgs is not None else [image_of(t) for t in ins]
+    pin = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in ins])
+    pout = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in outs])
+    flat = []
+    for k in ks:
+        flat.extend(float(v) for v in (k.tolist() if hasattr(k, "tolist") else k))
+    if len(flat) != 5 * n:
+        raise ValueError("each image needs 5 taps")
+    kk = (ctypes.c_float * max(5 * n, 1))(*flat)
+    ia = (conv_image * max(n, 1))(*imgs)
+    return n, pin, pout, kk, ia
+
+
+def conv_sep5_batch(ins: Sequence, outs: Sequence, ks: Sequence, imgs=None,
+                    mode: int = CONV_1PASS_FUSED, stream=None):
+    """Many images of different sizes in one persistent launch."""
+    n, pin, pout, kk, ia = _batch_args(ins, outs, ks, imgs)
+    return _check(lib().conv_sep5_batch(n, pin, pout, kk, ia, int(mode), _stream(stream)))
+
+
+class BatchPlan:
+    """A batch bound to fixed buffers, replayed as a captured hipGraph."""
+
+    def __init__(self, ins, outs, ks, imgs=None, mode: int = CONV_1PASS_FUSED):
+        n, pin, pout, kk, ia = _batch_args(ins, outs, ks, imgs)
+        h = ctypes.c_void_p()
+        _check(lib().conv_batch_plan_create(n, pin, pout, kk, ia, int(mode), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        return _check(lib().conv_batch_plan_launch(self._h, _stream(stream)))
+
+    def destroy(self):
+        if self._h:
+            lib().conv_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def conv_batch_plan_create(ins, outs, ks, imgs=None, mode: int = CONV_1PASS_FUSED) -> BatchPlan:
+    return BatchPlan(ins, outs, ks, imgs, mode)
+
+
+def conv_get_tile_cfg(dtype: int, kind: int) -> conv_tile_cfg:
+    c = conv_tile_cfg()
+    _check(lib().conv_get_tile_cfg(int(dtype), int(kind), ctypes.byref(c)))
+    return c
+
+
+def conv_set_tile_cfg(dtype: int, kind: int, rows_per_tile: int, waves_per_wg: int,
+                      persist_wgs_per_cu: int = 0):
+    c = conv_tile_cfg(int(rows_per_tile), int(waves_per_wg), int(persist_wgs_per_cu))
+    return _check(lib().conv_set_tile_cfg(int(dtype), int(kind), ctypes.byref(c)))
+
+
+def conv_tune(kind: int, ins, outs, ks, imgs=None, reps: int = 5, stream=None):
+    """Time every tile configuration on this workload; install and return the best."""
+    n, pin, pout, kk, ia = _batch_args(ins, outs, ks, imgs)
+    best = conv_tile_cfg()
+    ms = ctypes.c_float()
+    _check(lib().conv_tune(int(kind), n, pin, pout, kk, ia, int(reps), _stream(stream),
+                           ctypes.byref(best), ctypes.byref(ms)))
+    return best, float(ms.value)
+
+
+class Server:
+    """Continuous-batching server (see conv_serve_* in the C header)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
+                 max_batch: int = 64, device: int = -1):
+        cfg = conv_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(n_streams),
+                             int(max_batch), int(device))
+        h = ctypes.c_void_p()
+        _check(lib().conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, d_in, d_out, k, img: conv_image | None = None) -> int:
+        img = img or image_of(d_in)
+        t = ctypes.c_uint64()
+        _check(lib().conv_serve_submit(self._h, _ptr(d_in), _ptr(d_out), _taps(k),
+                                       ctypes.byref(img), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """None while pending; the request's timestamps (dict) once done."""
+        t = conv_req_times()
+        st = lib().conv_serve_poll(self._h, int(ticket), ctypes.byref(t))
+        if st == CONV_EAGAIN:
+            return None
+        _check(st)
+        return t.as_dict()
+
+    def drain(self):
+        return _check(lib().conv_serve_drain(self._h))
+
+    def stats(self) -> dict:
+        st = conv_serve_stats()
+        _check(lib().conv_serve_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def destroy(self):
+        if self._h:
+            _check(lib().conv_serve_destroy(self._h))
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
+                      max_batch: int = 64, device: int = -1) -> Server:
+    return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device)
+
+
+def conv_serve_submit(srv: Server, d_in, d_out, k, img=None) -> int:
+    return srv.submit(d_in, d_out, k, img)
+
+
+def conv_serve_poll(srv: Server, ticket: int):
+    return srv.poll(ticket)
+
+
+def conv_serve_drain(srv: Server):
+    return srv.drain()
+
+
+def conv_serve_get_stats(srv: Server) -> dict:
+    return srv.stats()
+
+
+def conv_serve_destroy(srv: Server):
+    return srv.destroy()
+
+
+def conv_version() -> str:
+    return lib().conv_version().decode()

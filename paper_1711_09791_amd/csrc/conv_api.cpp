@@ -1,0 +1,500 @@
+// conv_api.cpp -- C ABI of libconvsep5: argument validation, tile geometry,
+// dispatch, the batch descriptor ring, captured batch plans and the tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "conv_internal.h"
+#include "conv_sep5.h"
+#include "conv_common.h"
+
+using namespace convsep5;
+
+namespace convsep5 {
+
+static thread_local std::string g_err;
+
+conv_status set_error(conv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+conv_status hip_error(hipError_t e, const char *what) {
+    return set_error(CONV_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- validation ----------------------------------------------------------------
+conv_status check_image(const conv_image *img, Layout *L) {
+    if (!img) return set_error(CONV_EINVAL, "image descriptor is NULL");
+    if (img->dtype < CONV_F32 || img->dtype > CONV_BF16)
+        return set_error(CONV_EINVAL, "dtype %d is not CONV_F32/F16/BF16", img->dtype);
+    if (img->planes < 0 || img->rows < 0 || img->cols < 0)
+        return set_error(CONV_EINVAL, "negative shape %d x %d x %d", img->planes, img->rows,
+                         img->cols);
+    L->esz = esize_of(img->dtype);
+    L->vec = vec_of(img->dtype);
+    if (img->rows > kMaxRows)
+        return set_error(CONV_EINVAL, "rows %d exceed the limit %d", img->rows, kMaxRows);
+    if ((int64_t)img->cols * 4 > kMaxRowBytes)
+        return set_error(CONV_EINVAL, "cols %d exceed the limit %lld", img->cols,
+                         (long long)(kMaxRowBytes / 4));
+    L->pitch = img->pitch == 0 ? img->cols : img->pitch;
+    if (L->pitch < img->cols)
+        return set_error(CONV_EINVAL, "pitch %lld < cols %d", (long long)img->pitch, img->cols);
+    if (L->pitch > ((int64_t)1 << 40))
+        return set_error(CONV_EINVAL, "pitch %lld too large", (long long)L->pitch);
+    const int64_t rows = img->rows, cols = img->cols, planes = img->planes;
+    const int64_t min_ps = rows > 0 ? (rows - 1) * L->pitch + cols : 0;
+    L->ps = img->plane_stride == 0 ? rows * L->pitch : img->plane_stride;
+    if (img->plane_stride != 0 && L->ps < min_ps)
+        return set_error(CONV_EINVAL, "plane_stride %lld < %lld", (long long)img->plane_stride,
+                         (long long)min_ps);
+    if (L->ps > ((int64_t)1 << 50))
+        return set_error(CONV_EINVAL, "plane_stride %lld too large", (long long)L->ps);
+    L->empty = planes == 0 || rows == 0 || cols == 0;
+    if (L->empty) {
+        L->extent_bytes = 0;
+        return CONV_OK;
+    }
+    const __int128 ext = (__int128)(planes - 1) * L->ps + (__int128)(rows - 1) * L->pitch + cols;
+    if (ext * L->esz > ((__int128)1 << 60))
+        return set_error(CONV_EINVAL, "image spans too many bytes");
+    L->extent_bytes = (int64_t)ext * L->esz;
+    return CONV_OK;
+}
+
+bool overlaps(const void *a, int64_t na, const void *b, int64_t nb) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    if (na <= 0 || nb <= 0) return false;
+    return pa < pb + (uintptr_t)nb && pb < pa + (uintptr_t)na;
+}
+
+// ---- tile configuration ---------------------------------------------------------
+static std::mutex g_cfg_mu;
+static conv_tile_cfg g_cfg[3][2] = {
+    {{32, 4, 0}, {64, 1, 8}},
+    {{32, 4, 0}, {64, 1, 8}},
+    {{32, 4, 0}, {64, 1, 8}},
+};
+
+conv_tile_cfg get_cfg(int dtype, int kind) {
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    return g_cfg[dtype][kind];
+}
+
+static bool cfg_ok(const conv_tile_cfg *c, int kind) {
+    if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
+    if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
+    if (kind == 1 && (c->persist_wgs_per_cu < 1 || c->persist_wgs_per_cu > 32)) return false;
+    return true;
+}
+
+void fill_taps(Taps *t, const float *k) {
+    for (int i = 0; i < 5; ++i) t->k[i] = k[i];
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) t->K[5 * a + b] = (float)((double)k[a] * (double)k[b]);
+}
+
+int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
+                  const Layout &L, const float *k, const conv_tile_cfg &cfg) {
+    std::memset(d, 0, sizeof *d);
+    d->in = in;
+    d->out = out;
+    d->tmp = tmp;
+    d->pitch = L.pitch;
+    d->pstride = L.ps;
+    d->planes = img->planes;
+    d->rows = img->rows;
+    d->cols = img->cols;
+    const int v = L.vec;
+    const bool al = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
+                    (tmp == nullptr || (uintptr_t)tmp % 16 == 0) && img->cols % v == 0 &&
+                    L.pitch % v == 0 && L.ps % v == 0;
+    d->aligned = al ? 1 : 0;
+    const int sw = 64 * v;
+    d->ns = (img->cols + sw - 1) / sw;
+    d->nsg = (d->ns + cfg.waves_per_wg - 1) / cfg.waves_per_wg;
+    d->th = cfg.rows_per_tile;
+    d->nb = (img->rows + d->th - 1) / d->th;
+    fill_taps(&d->tp, k);
+    if (L.empty) return 0;
+    return (int64_t)img->planes * d->nsg * d->nb;
+}
+
+// ---- per-device state --------------------------------------------------------------
+struct DescSlot {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+struct DeviceState {
+    int cus = 0;
+    std::mutex mu;
+    DescSlot slots[kDescSlots];
+    int next = 0;
+};
+
+static std::mutex g_dev_mu;
+static std::vector<DeviceState *> g_devs;
+
+conv_status device_state(DeviceState **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    if ((int)g_devs.size() <= dev) g_devs.resize(dev + 1, nullptr);
+    if (!g_devs[dev]) {
+        int cus = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_error(e, "hipDeviceGetAttribute");
+        auto *st = new DeviceState;
+        st->cus = cus > 0 ? cus : 1;
+        g_devs[dev] = st;
+    }
+    *out = g_devs[dev];
+    return CONV_OK;
+}
+
+int device_cus() {
+    DeviceState *st = nullptr;
+    return device_state(&st) == CONV_OK ? st->cus : 256;
+}
+
+// Stage `bytes` of descriptors through a pinned slot and copy them to device
+// memory on stream s.  Returns the device copy; the caller records the slot's
+// event after the kernel that reads it.
+static conv_status stage_descs(DeviceState *st, const void *src, size_t bytes, hipStream_t s,
+                               DescSlot **slot_out) {
+    std::lock_guard<std::mutex> g(st->mu);
+    DescSlot &sl = st->slots[st->next];
+    st->next = (st->next + 1) % kDescSlots;
+    hipError_t e;
+    if (sl.pending) {
+        e = hipEventSynchronize(sl.ev);
+        if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(descriptor slot)");
+        sl.pending = false;
+    }
+    if (!sl.ev) {
+        e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+    }
+    if (sl.cap < bytes) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) (void)hipFree(sl.dev);
+        sl.host = sl.dev = nullptr;
+        sl.cap = 0;
+        size_t cap = std::max(bytes, (size_t)kDescSlotMinBytes);
+        e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return set_error(CONV_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+        e = hipMalloc(&sl.dev, cap);
+        if (e != hipSuccess) {
+            (void)hipHostFree(sl.host);
+            sl.host = nullptr;
+            return set_error(CONV_ENOMEM, "hipMalloc(%zu) failed", cap);
+        }
+        sl.cap = cap;
+    }
+    std::memcpy(sl.host, src, bytes);
+    e = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(descriptors)");
+    *slot_out = &sl;
+    return CONV_OK;
+}
+
+static conv_status finish_slot(DescSlot *sl, hipStream_t s) {
+    hipError_t e = hipEventRecord(sl->ev, s);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    sl->pending = true;
+    return CONV_OK;
+}
+
+// ---- batch validation and descriptor building --------------------------------------
+conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, const float *k,
+                        const conv_image *imgs, int mode, const conv_tile_cfg &cfg,
+                        std::vector<ImgDev> *descs, int64_t *total, int *dtype_out) {
+    if (n < 0) return set_error(CONV_EINVAL, "n = %d < 0", n);
+    if (mode != CONV_1PASS_FUSED && mode != CONV_1PASS_DIRECT25)
+        return set_error(CONV_EINVAL, "mode %d is not FUSED or DIRECT25", mode);
+    descs->clear();
+    *total = 0;
+    if (n == 0) return CONV_OK;
+    if (!d_in || !d_out || !k || !imgs)
+        return set_error(CONV_EINVAL, "NULL array argument");
+    const int dtype = imgs[0].dtype;
+    *dtype_out = dtype;
+    struct Span {
+        uintptr_t lo, hi;
+        int idx;
+    };
+    std::vector<Span> outs, ins;
+    descs->resize(n);
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) {
+        Layout L;
+        conv_status st = check_image(&imgs[i], &L);
+        if (st != CONV_OK)
+            return set_error(st, "image %d: %s", i, conv_last_error());
+        if (imgs[i].dtype != dtype)
+            return set_error(CONV_EINVAL, "image %d dtype %d differs from image 0 (%d)", i,
+                             imgs[i].dtype, dtype);
+        if (!L.empty) {
+            if (!d_in[i] || !d_out[i])
+                return set_error(CONV_EINVAL, "image %d: NULL device pointer", i);
+            if (overlaps(d_in[i], L.extent_bytes, d_out[i], L.extent_bytes))
+                return set_error(CONV_EALIAS, "image %d: input and output overlap", i);
+            outs.push_back({(uintptr_t)d_out[i], (uintptr_t)d_out[i] + L.extent_bytes, i});
+            ins.push_back({(uintptr_t)d_in[i], (uintptr_t)d_in[i] + L.extent_bytes, i});
+        }
+        ImgDev &d = (*descs)[i];
+        const int64_t tiles = fill_desc(&d, d_in[i], d_out[i], nullptr, &imgs[i], L, k + 5 * i, cfg);
+        d.tile_begin = t;
+        t += tiles;
+        d.tile_end = t;
+    }
+    std::sort(outs.begin(), outs.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].lo < outs[i - 1].hi)
+            return set_error(CONV_EALIAS, "outputs of images %d and %d overlap", outs[i - 1].idx,
+                             outs[i].idx);
+    for (const Span &in : ins) {
+        // first output starting at or after in.hi is past it; check the one before
+        auto it = std::lower_bound(outs.begin(), outs.end(), in.hi,
+                                   [](const Span &o, uintptr_t v) { return o.lo < v; });
+        if (it != outs.begin()) {
+            const Span &o = *(it - 1);
+            if (o.hi > in.lo && o.idx != in.idx)
+                return set_error(CONV_EALIAS, "output of image %d overlaps input of image %d",
+                                 o.idx, in.idx);
+        }
+    }
+    *total = t;
+    return CONV_OK;
+}
+
+conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
+                          const conv_tile_cfg &cfg, hipStream_t s) {
+    if (total == 0) return CONV_OK;
+    DeviceState *st = nullptr;
+    conv_status rc = device_state(&st);
+    if (rc != CONV_OK) return rc;
+    DescSlot *slot = nullptr;
+    rc = stage_descs(st, descs.data(), descs.size() * sizeof(ImgDev), s, &slot);
+    if (rc != CONV_OK) return rc;
+    const int64_t cap = (int64_t)st->cus * cfg.persist_wgs_per_cu;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+    hipError_t e = launch_batch((const ImgDev *)slot->dev, (int)descs.size(), total, dtype, mode,
+                                cfg.waves_per_wg, grid, s);
+    rc = finish_slot(slot, s);
+    if (e != hipSuccess) return hip_error(e, "batch kernel launch");
+    return rc;
+}
+
+}  // namespace convsep5
+
+// ==== public entry points ===========================================================
+extern "C" {
+
+const char *conv_last_error(void) { return g_err.c_str(); }
+
+const char *conv_version(void) { return "convsep5 1.0 gfx950"; }
+
+conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
+                            const conv_image *img, int mode, hipStream_t stream) {
+    clear_error();
+    Layout L;
+    conv_status st = check_image(img, &L);
+    if (st != CONV_OK) return st;
+    if (!k) return set_error(CONV_EINVAL, "taps pointer is NULL");
+    if (mode != CONV_1PASS_FUSED && mode != CONV_1PASS_DIRECT25)
+        return set_error(CONV_EINVAL, "mode %d is not FUSED or DIRECT25", mode);
+    if (L.empty) return CONV_OK;
+    if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
+    if (overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
+        return set_error(CONV_EALIAS, "input and output overlap");
+    const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    ImgDev d;
+    const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
+    hipError_t e = launch_image(d, img->dtype, mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
+                                cfg.waves_per_wg, nblocks, stream);
+    if (e != hipSuccess) return hip_error(e, "1pass kernel launch");
+    return CONV_OK;
+}
+
+conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp, const float k[5],
+                            const conv_image *img, hipStream_t stream) {
+    clear_error();
+    Layout L;
+    conv_status st = check_image(img, &L);
+    if (st != CONV_OK) return st;
+    if (!k) return set_error(CONV_EINVAL, "taps pointer is NULL");
+    if (L.empty) return CONV_OK;
+    if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
+    if (d_in != (const void *)d_out && overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
+        return set_error(CONV_EALIAS, "input and output partially overlap");
+    const int64_t tmp_bytes = (int64_t)img->planes * img->rows * img->cols * 4;
+    if (d_tmp && (overlaps(d_tmp, tmp_bytes, d_in, L.extent_bytes) ||
+                  overlaps(d_tmp, tmp_bytes, d_out, L.extent_bytes)))
+        return set_error(CONV_EALIAS, "workspace overlaps the input or output");
+    float *tmp = d_tmp;
+    hipError_t e;
+    if (!tmp) {
+        e = hipMallocAsync((void **)&tmp, (size_t)tmp_bytes, stream);
+        if (e != hipSuccess)
+            return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)tmp_bytes,
+                             hipGetErrorString(e));
+    }
+    const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    ImgDev d;
+    const int64_t nblocks = fill_desc(&d, d_in, d_out, tmp, img, L, k, cfg);
+    e = launch_image(d, img->dtype, MODE_ROWPASS, cfg.waves_per_wg, nblocks, stream);
+    if (e == hipSuccess)
+        e = launch_image(d, img->dtype, MODE_COLPASS, cfg.waves_per_wg, nblocks, stream);
+    if (!d_tmp) (void)hipFreeAsync(tmp, stream);
+    if (e != hipSuccess) return hip_error(e, "2pass kernel launch");
+    return CONV_OK;
+}
+
+conv_status conv_sep5_batch(int32_t n, const void *const *d_in, void *const *d_out,
+                            const float *k, const conv_image *imgs, int mode,
+                            hipStream_t stream) {
+    clear_error();
+    std::vector<ImgDev> descs;
+    int64_t total = 0;
+    int dtype = 0;
+    const int dt0 = (n > 0 && imgs && imgs[0].dtype >= 0 && imgs[0].dtype <= 2) ? imgs[0].dtype : 0;
+    const conv_tile_cfg cfg = get_cfg(dt0, 1);
+    conv_status st = build_batch(n, d_in, d_out, k, imgs, mode, cfg, &descs, &total, &dtype);
+    if (st != CONV_OK) return st;
+    return enqueue_batch(descs, total, dtype, mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
+                         cfg, stream);
+}
+
+conv_status conv_get_tile_cfg(int32_t dtype, int32_t kind, conv_tile_cfg *cfg) {
+    clear_error();
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+        return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
+    *cfg = get_cfg(dtype, kind);
+    return CONV_OK;
+}
+
+conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *cfg) {
+    clear_error();
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+        return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
+    if (!cfg_ok(cfg, kind)) return set_error(CONV_EINVAL, "tile configuration out of range");
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_cfg[dtype][kind] = *cfg;
+    if (kind == 0) g_cfg[dtype][0].persist_wgs_per_cu = 0;
+    return CONV_OK;
+}
+
+// ---- captured batch plans -------------------------------------------------------------
+struct conv_plan {
+    int device;
+    ImgDev *d_descs;
+    hipStream_t cap;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+conv_status conv_batch_plan_create(int32_t n, const void *const *d_in, void *const *d_out,
+                                   const float *k, const conv_image *imgs, int mode,
+                                   conv_plan **plan) {
+    clear_error();
+    if (!plan) return set_error(CONV_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    std::vector<ImgDev> descs;
+    int64_t total = 0;
+    int dtype = 0;
+    const int dt0 = (n > 0 && imgs && imgs[0].dtype >= 0 && imgs[0].dtype <= 2) ? imgs[0].dtype : 0;
+    const conv_tile_cfg cfg = get_cfg(dt0, 1);
+    conv_status st = build_batch(n, d_in, d_out, k, imgs, mode, cfg, &descs, &total, &dtype);
+    if (st != CONV_OK) return st;
+    DeviceState *ds = nullptr;
+    st = device_state(&ds);
+    if (st != CONV_OK) return st;
+    auto *p = new conv_plan();
+    hipGetDevice(&p->device);
+    const size_t bytes = std::max<size_t>(descs.size(), 1) * sizeof(ImgDev);
+    hipError_t e = hipMalloc((void **)&p->d_descs, bytes);
+    if (e != hipSuccess) {
+        delete p;
+        return set_error(CONV_ENOMEM, "hipMalloc(plan descriptors) failed");
+    }
+    if (!descs.empty()) {
+        e = hipMemcpy(p->d_descs, descs.data(), descs.size() * sizeof(ImgDev),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(p->d_descs);
+            delete p;
+            return hip_error(e, "hipMemcpy(plan descriptors)");
+        }
+    }
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        hipFree(p->d_descs);
+        delete p;
+        return hip_error(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    hipError_t le = hipSuccess;
+    if (e == hipSuccess) {
+        if (total > 0) {
+            const int64_t capn = (int64_t)ds->cus * cfg.persist_wgs_per_cu;
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, capn));
+            le = launch_batch(p->d_descs, (int)descs.size(), total, dtype,
+                              mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
+                              cfg.waves_per_wg, grid, p->cap);
+        }
+        e = hipStreamEndCapture(p->cap, &p->graph);
+    }
+    if (e == hipSuccess && le == hipSuccess)
+        e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess || le != hipSuccess) {
+        const hipError_t bad = le != hipSuccess ? le : e;
+        if (p->graph) hipGraphDestroy(p->graph);
+        hipStreamDestroy(p->cap);
+        hipFree(p->d_descs);
+        delete p;
+        return hip_error(bad, "graph capture of the batch launch");
+    }
+    *plan = p;
+    return CONV_OK;
+}
+
+conv_status conv_batch_plan_launch(conv_plan *plan, hipStream_t stream) {
+    clear_error();
+    if (!plan) return set_error(CONV_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, stream);
+    if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+    return CONV_OK;
+}
+
+conv_status conv_batch_plan_destroy(conv_plan *plan) {
+    clear_error();
+    if (!plan) return CONV_OK;
+    hipGraphExecDestroy(plan->exec);
+    hipGraphDestroy(plan->graph);
+    hipStreamDestroy(plan->cap);
+    hipFree(plan->d_descs);
+    delete plan;
+    return CONV_OK;
+}
+
+}  // extern "C"

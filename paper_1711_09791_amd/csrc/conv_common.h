@@ -1,0 +1,42 @@
+// conv_common.h -- host-side helpers shared by the C ABI translation units.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "conv_internal.h"
+#include "conv_sep5.h"
+
+namespace convsep5 {
+
+// Limits that keep every 32-bit buffer offset and row index in range.
+constexpr int kMaxRows = 1 << 30;
+constexpr int64_t kMaxRowBytes = (int64_t)1 << 30;
+constexpr int kDescSlots = 32;                 // batch descriptor ring depth
+constexpr size_t kDescSlotMinBytes = 256 * sizeof(ImgDev);
+
+struct Layout {
+    int64_t pitch = 0, ps = 0;   // elements
+    int64_t extent_bytes = 0;    // bytes from the base to one past the last element
+    int esz = 4, vec = 4;
+    bool empty = true;
+};
+
+conv_status set_error(conv_status st, const char *fmt, ...);
+void clear_error();
+conv_status hip_error(hipError_t e, const char *what);
+conv_status check_image(const conv_image *img, Layout *L);
+bool overlaps(const void *a, int64_t na, const void *b, int64_t nb);
+conv_tile_cfg get_cfg(int dtype, int kind);
+void fill_taps(Taps *t, const float *k);
+int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
+                  const Layout &L, const float *k, const conv_tile_cfg &cfg);
+int device_cus();
+conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, const float *k,
+                        const conv_image *imgs, int mode, const conv_tile_cfg &cfg,
+                        std::vector<ImgDev> *descs, int64_t *total, int *dtype_out);
+conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
+                          const conv_tile_cfg &cfg, hipStream_t s);
+
+}  // namespace convsep5

@@ -1,0 +1,55 @@
+// conv_internal.h -- types shared by the kernels and the host side of
+// libconvsep5 (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace convsep5 {
+
+enum Mode : int {
+    MODE_FUSED = 0,     // row filter -> register window -> column filter
+    MODE_DIRECT25 = 1,  // 25 multiply-adds per pixel (paper's single pass)
+    MODE_ROWPASS = 2,   // two-pass, first kernel: input -> FP32 intermediate
+    MODE_COLPASS = 3    // two-pass, second kernel: FP32 intermediate -> output
+};
+
+// Taps as the kernels read them: k for the separable forms, K = fl32(k_a k_b)
+// (rounded once on the host from the FP64 product) for the direct form.
+struct Taps {
+    float k[5];
+    float K[25];
+};
+
+// One image as the kernels see it (kernel argument for single launches, one
+// row of the device descriptor table for batch launches).  Strides are in
+// elements of the storage type.
+struct ImgDev {
+    const void *in;
+    void *out;
+    float *tmp;           // two-pass FP32 intermediate, dense [plane][row][col]
+    int64_t pitch;
+    int64_t pstride;
+    int32_t planes, rows, cols;
+    int32_t aligned;      // 1: 16-byte vector path allowed
+    int32_t ns;           // column strips of 64*VEC columns
+    int32_t nsg;          // strip groups (waves_per_wg strips each)
+    int32_t nb;           // row bands
+    int32_t th;           // output rows per band
+    int64_t tile_begin;   // batch: this image's first tile in the launch
+    int64_t tile_end;     // batch: one past its last tile
+    Taps tp;
+};
+
+// Elements per lane per row: 16 bytes of storage.
+inline int vec_of(int dtype) { return dtype == 0 ? 4 : 8; }
+inline int esize_of(int dtype) { return dtype == 0 ? 4 : 2; }
+
+// Kernel launchers (conv_kernels.hip).  `waves` is 1, 2 or 4.
+hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves,
+                        int64_t nblocks, hipStream_t s);
+hipError_t launch_batch(const ImgDev *d_descs, int n, int64_t total_tiles,
+                        int dtype, int mode, int waves, int grid,
+                        hipStream_t s);
+
+}  // namespace convsep5

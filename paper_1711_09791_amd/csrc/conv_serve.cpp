@@ -1,0 +1,346 @@
+// conv_serve.cpp -- continuous-batching server for the width-5 separable
+// convolution.
+//
+// Requests (device-resident images of any size, each with its own taps) are
+// submitted without blocking.  One scheduler thread per server:
+//   1. retires launches whose completion event has fired (frees their slots
+//      and HBM budget, stamps their tickets done);
+//   2. while a launch stream is idle, admits queued requests in arrival order
+//      as long as a slot is free and their footprint (input + output bytes)
+//      fits the budget, up to max_batch requests of one dtype, and enqueues
+//      them as ONE persistent batch launch on that stream, followed by an
+//      event;
+//   3. waits for new work or polls the events of the launches in flight.
+// Requests that arrive while a launch runs go into the next launch on another
+// stream, so their work overlaps on the device.  A request's result is the
+// same batch-kernel tile code as a lone call, so it is bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "conv_common.h"
+
+using namespace convsep5;
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3 };
+
+struct Req {
+    uint64_t ticket = 0;
+    const void *in = nullptr;
+    void *out = nullptr;
+    float k[5] = {0, 0, 0, 0, 0};
+    conv_image img{};
+    uint64_t footprint = 0;
+    conv_req_times t{};
+    int state = QUEUED;
+};
+
+struct Launch {
+    std::vector<Req *> reqs;
+    uint64_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    int stream = 0;
+};
+
+}  // namespace
+
+struct conv_server {
+    conv_serve_cfg cfg{};
+    int device = 0;
+    std::vector<hipStream_t> streams;
+    std::vector<char> stream_busy;
+    std::vector<hipEvent_t> event_pool;
+    std::mutex mu;
+    std::condition_variable cv;       // new work or stop
+    std::condition_variable idle_cv;  // queue and in-flight both empty
+    std::deque<Req *> queue;
+    std::unordered_map<uint64_t, Req *> reqs;
+    std::vector<Launch> inflight;
+    uint64_t bytes_in_flight = 0;
+    int slots_in_flight = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    conv_serve_stats stats{};
+    std::thread th;
+
+    void run();
+    void retire_locked();
+    void launch_locked();
+};
+
+void conv_server::retire_locked() {
+    for (size_t i = 0; i < inflight.size();) {
+        Launch &L = inflight[i];
+        const hipError_t q = hipEventQuery(L.ev);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        const uint64_t t = now_ns();
+        for (Req *r : L.reqs) {
+            r->t.done_ns = t;
+            r->state = q == hipSuccess ? DONE : FAILED;
+        }
+        if (q == hipSuccess) stats.completed += L.reqs.size();
+        else stats.failed += L.reqs.size();
+        bytes_in_flight -= L.bytes;
+        slots_in_flight -= (int)L.reqs.size();
+        stream_busy[L.stream] = 0;
+        event_pool.push_back(L.ev);
+        inflight.erase(inflight.begin() + i);
+    }
+}
+
+void conv_server::launch_locked() {
+    while (!queue.empty()) {
+        int s = -1;
+        for (int i = 0; i < (int)streams.size(); ++i)
+            if (!stream_busy[i]) {
+                s = i;
+                break;
+            }
+        if (s < 0) return;
+        Launch L;
+        L.stream = s;
+        const int dtype = queue.front()->img.dtype;
+        while (!queue.empty() && (int)L.reqs.size() < cfg.max_batch &&
+               slots_in_flight + 1 <= cfg.max_slots &&
+               bytes_in_flight + L.bytes + queue.front()->footprint <= cfg.hbm_budget_bytes &&
+               queue.front()->img.dtype == dtype) {
+            Req *r = queue.front();
+            queue.pop_front();
+            L.reqs.push_back(r);
+            L.bytes += r->footprint;
+            slots_in_flight += 1;
+        }
+        if (L.reqs.empty()) return;  // head does not fit yet: wait for a retirement
+        bytes_in_flight += L.bytes;
+        const int n = (int)L.reqs.size();
+        std::vector<const void *> ins(n);
+        std::vector<void *> outs(n);
+        std::vector<float> ks(5 * n);
+        std::vector<conv_image> imgs(n);
+        const uint64_t t_admit = now_ns();
+        for (int i = 0; i < n; ++i) {
+            Req *r = L.reqs[i];
+            ins[i] = r->in;
+            outs[i] = r->out;
+            for (int j = 0; j < 5; ++j) ks[5 * i + j] = r->k[j];
+            imgs[i] = r->img;
+            r->t.admit_ns = t_admit;
+            r->t.batch_size = n;
+            r->t.stream = s;
+            r->state = INFLIGHT;
+        }
+        const conv_tile_cfg tc = get_cfg(dtype, 1);
+        std::vector<ImgDev> descs;
+        int64_t total = 0;
+        int dt = 0;
+        conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
+                                     CONV_1PASS_FUSED, tc, &descs, &total, &dt);
+        if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, streams[s]);
+        if (event_pool.empty()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = CONV_EHIP;
+            else event_pool.push_back(e);
+        }
+        if (st == CONV_OK) {
+            L.ev = event_pool.back();
+            event_pool.pop_back();
+            if (hipEventRecord(L.ev, streams[s]) != hipSuccess) {
+                event_pool.push_back(L.ev);
+                st = CONV_EHIP;
+            }
+        }
+        const uint64_t t_launch = now_ns();
+        if (st != CONV_OK) {
+            for (Req *r : L.reqs) {
+                r->t.launch_ns = r->t.done_ns = t_launch;
+                r->state = FAILED;
+            }
+            stats.failed += L.reqs.size();
+            bytes_in_flight -= L.bytes;
+            slots_in_flight -= n;
+            continue;
+        }
+        for (Req *r : L.reqs) r->t.launch_ns = t_launch;
+        stream_busy[s] = 1;
+        stats.launches += 1;
+        stats.max_bytes_in_flight = std::max<uint64_t>(stats.max_bytes_in_flight, bytes_in_flight);
+        stats.max_slots_in_flight = std::max(stats.max_slots_in_flight, slots_in_flight);
+        stats.max_batch = std::max(stats.max_batch, n);
+        inflight.push_back(std::move(L));
+        stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)inflight.size());
+    }
+}
+
+void conv_server::run() {
+    hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        retire_locked();
+        launch_locked();
+        if (queue.empty() && inflight.empty()) {
+            idle_cv.notify_all();
+            if (stop) break;
+            cv.wait(lk);
+            continue;
+        }
+        // Work is on the device: poll its events without holding the lock.
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+    }
+}
+
+extern "C" {
+
+conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
+    clear_error();
+    if (!cfg || !srv) return set_error(CONV_EINVAL, "NULL argument");
+    *srv = nullptr;
+    if (cfg->hbm_budget_bytes == 0 || cfg->max_slots < 1 || cfg->n_streams < 1 ||
+        cfg->n_streams > 16 || cfg->max_batch < 1)
+        return set_error(CONV_EINVAL, "bad server configuration");
+    int prev = 0;
+    hipGetDevice(&prev);
+    int dev = cfg->device < 0 ? prev : cfg->device;
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+    auto *s = new conv_server();
+    s->cfg = *cfg;
+    s->device = dev;
+    for (int i = 0; i < cfg->n_streams; ++i) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (hipStream_t x : s->streams) hipStreamDestroy(x);
+            delete s;
+            hipSetDevice(prev);
+            return hip_error(e, "hipStreamCreate");
+        }
+        s->streams.push_back(st);
+        s->stream_busy.push_back(0);
+    }
+    hipSetDevice(prev);
+    s->th = std::thread([s] { s->run(); });
+    *srv = s;
+    return CONV_OK;
+}
+
+conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, const float k[5],
+                              const conv_image *img, uint64_t *ticket) {
+    clear_error();
+    if (!srv || !ticket || !k) return set_error(CONV_EINVAL, "NULL argument");
+    Layout L;
+    conv_status st = check_image(img, &L);
+    if (st != CONV_OK) return st;
+    if (!L.empty) {
+        if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
+        if (overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
+            return set_error(CONV_EALIAS, "input and output overlap");
+    }
+    const uint64_t fp = 2 * (uint64_t)L.extent_bytes;
+    if (fp > srv->cfg.hbm_budget_bytes)
+        return set_error(CONV_ENOMEM, "footprint %llu exceeds the budget %llu",
+                         (unsigned long long)fp, (unsigned long long)srv->cfg.hbm_budget_bytes);
+    auto *r = new Req();
+    r->in = d_in;
+    r->out = d_out;
+    for (int i = 0; i < 5; ++i) r->k[i] = k[i];
+    r->img = *img;
+    r->footprint = fp;
+    r->t.submit_ns = now_ns();
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        if (srv->stop) {
+            delete r;
+            return set_error(CONV_EINVAL, "server is shutting down");
+        }
+        r->ticket = srv->next_ticket++;
+        srv->stats.submitted += 1;
+        srv->reqs[r->ticket] = r;
+        if (L.empty) {
+            r->t.admit_ns = r->t.launch_ns = r->t.done_ns = r->t.submit_ns;
+            r->state = DONE;
+            srv->stats.completed += 1;
+        } else {
+            srv->queue.push_back(r);
+        }
+        *ticket = r->ticket;
+    }
+    srv->cv.notify_one();
+    return CONV_OK;
+}
+
+conv_status conv_serve_poll(conv_server *srv, uint64_t ticket, conv_req_times *t) {
+    clear_error();
+    if (!srv) return set_error(CONV_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> g(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return set_error(CONV_ENOTFOUND, "unknown ticket %llu",
+                                                (unsigned long long)ticket);
+    Req *r = it->second;
+    if (r->state == QUEUED || r->state == INFLIGHT) return CONV_EAGAIN;
+    if (t) *t = r->t;
+    const int state = r->state;
+    srv->reqs.erase(it);
+    delete r;
+    if (state == FAILED) return set_error(CONV_EHIP, "the launch of ticket %llu failed",
+                                          (unsigned long long)ticket);
+    return CONV_OK;
+}
+
+conv_status conv_serve_drain(conv_server *srv) {
+    clear_error();
+    if (!srv) return set_error(CONV_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv.notify_one();
+    srv->idle_cv.wait(lk, [srv] { return srv->queue.empty() && srv->inflight.empty(); });
+    return CONV_OK;
+}
+
+conv_status conv_serve_get_stats(conv_server *srv, conv_serve_stats *stats) {
+    clear_error();
+    if (!srv || !stats) return set_error(CONV_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(srv->mu);
+    *stats = srv->stats;
+    return CONV_OK;
+}
+
+conv_status conv_serve_destroy(conv_server *srv) {
+    clear_error();
+    if (!srv) return CONV_OK;
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv.notify_one();
+    if (srv->th.joinable()) srv->th.join();
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(srv->device);
+    for (hipEvent_t e : srv->event_pool) hipEventDestroy(e);
+    for (hipStream_t s : srv->streams) hipStreamDestroy(s);
+    hipSetDevice(prev);
+    for (auto &kv : srv->reqs) delete kv.second;
+    delete srv;
+    return CONV_OK;
+}
+
+}  // extern "C"

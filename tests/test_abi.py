@@ -1,0 +1,178 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1711_09791_amd as cs
+from paper_1711_09791_amd import conv_image
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "conv_sep5.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(cs.LIB_PATH),
+                                reason="libconvsep5.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(conv_[a-z0-9_]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("conv_sep5_2pass", "conv_sep5_1pass", "conv_sep5_batch",
+                     "conv_serve_submit", "conv_serve_poll", "conv_last_error"):
+        assert required in names
+    assert set(names) == set(cs.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = cs.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert "gfx950" in cs.conv_version()
+
+
+def img(planes=3, rows=16, cols=16, dtype=0, pitch=0, plane_stride=0):
+    return conv_image(planes, rows, cols, dtype, pitch, plane_stride)
+
+
+K = (ctypes.c_float * 5)(1, 4, 6, 4, 1)
+A, B = 0x100000, 0x900000  # never dereferenced: validation fails first
+
+
+def call1(i, mode=0, a=A, b=B, k=K):
+    return cs.lib().conv_sep5_1pass(ctypes.c_void_p(a), ctypes.c_void_p(b), k,
+                                    ctypes.byref(i) if i is not None else None, mode, None)
+
+
+def call2(i, a=A, b=B, t=0, k=K):
+    return cs.lib().conv_sep5_2pass(ctypes.c_void_p(a), ctypes.c_void_p(b), ctypes.c_void_p(t),
+                                    k, ctypes.byref(i), None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dtype=3), dict(dtype=-1), dict(planes=-1), dict(rows=-2), dict(cols=-5),
+    dict(pitch=8), dict(rows=4, plane_stride=10), dict(rows=(1 << 30) + 1),
+    dict(cols=(1 << 28) + 1),
+])
+def test_1pass_rejects_bad_descriptor(bad):
+    assert call1(img(**bad)) == cs.CONV_EINVAL
+    assert cs.conv_last_error()
+
+
+def test_1pass_rejects_null_and_mode():
+    assert call1(None) == cs.CONV_EINVAL
+    assert call1(img(), k=None) == cs.CONV_EINVAL
+    assert call1(img(), mode=2) == cs.CONV_EINVAL
+    assert call1(img(), a=0) == cs.CONV_EINVAL
+    assert call1(img(), b=0) == cs.CONV_EINVAL
+
+
+def test_1pass_alias_checks():
+    n = 3 * 16 * 16 * 4
+    assert call1(img(), a=A, b=A) == cs.CONV_EALIAS
+    assert call1(img(), a=A, b=A + n - 4) == cs.CONV_EALIAS
+    assert call1(img(), a=A + n - 4, b=A) == cs.CONV_EALIAS
+
+
+def test_empty_images_are_no_ops():
+    # no HIP call happens for an empty image, so this works without a GPU
+    for e in (img(planes=0), img(rows=0), img(cols=0)):
+        assert call1(e, a=0, b=0) == cs.CONV_OK
+        assert call2(e, a=0, b=0) == cs.CONV_OK
+
+
+def test_2pass_alias_checks():
+    n = 3 * 16 * 16 * 4
+    assert call2(img(), a=A, b=A + 64) == cs.CONV_EALIAS          # partial overlap
+    assert call2(img(), a=A, b=B, t=A + 8) == cs.CONV_EALIAS     # tmp over input
+    assert call2(img(), a=A, b=B, t=B + n - 4) == cs.CONV_EALIAS  # tmp over output
+    assert call2(img(pitch=3)) == cs.CONV_EINVAL
+
+
+def _batch(n, ins, outs, imgs, mode=0, ks=None):
+    L = cs.lib()
+    pin = (ctypes.c_void_p * max(n, 1))(*ins)
+    pout = (ctypes.c_void_p * max(n, 1))(*outs)
+    kk = (ctypes.c_float * max(5 * n, 1))(*(ks or [1.0] * (5 * n)))
+    ia = (conv_image * max(n, 1))(*imgs)
+    return L.conv_sep5_batch(n, pin, pout, kk, ia, mode, None)
+
+
+def test_batch_validation():
+    L = cs.lib()
+    assert L.conv_sep5_batch(-1, None, None, None, None, 0, None) == cs.CONV_EINVAL
+    assert L.conv_sep5_batch(0, None, None, None, None, 0, None) == cs.CONV_OK
+    assert L.conv_sep5_batch(2, None, None, None, None, 0, None) == cs.CONV_EINVAL
+    n = 3 * 16 * 16 * 4
+    i0 = img()
+    # dtype mismatch
+    assert _batch(2, [A, A + 2 * n], [B, B + 2 * n], [i0, img(dtype=1)]) == cs.CONV_EINVAL
+    # bad mode
+    assert _batch(1, [A], [B], [i0], mode=5) == cs.CONV_EINVAL
+    # two outputs overlap
+    assert _batch(2, [A, A + 2 * n], [B, B + 8], [i0, i0]) == cs.CONV_EALIAS
+    # an output overlaps another image's input
+    assert _batch(2, [A, B + 2 * n], [B, A + 16], [i0, i0]) == cs.CONV_EALIAS
+    # own input/output overlap
+    assert _batch(1, [A], [A + 4], [i0]) == cs.CONV_EALIAS
+    # a bad descriptor names its image
+    assert _batch(2, [A, A + 2 * n], [B, B + 2 * n], [i0, img(rows=-1)]) == cs.CONV_EINVAL
+    assert "image 1" in cs.conv_last_error()
+
+
+def test_tile_cfg_validation_and_roundtrip():
+    before = cs.conv_get_tile_cfg(0, 0)
+    with pytest.raises(cs.ConvError):
+        cs.conv_set_tile_cfg(0, 0, 0, 4)
+    with pytest.raises(cs.ConvError):
+        cs.conv_set_tile_cfg(0, 0, 32, 3)
+    with pytest.raises(cs.ConvError):
+        cs.conv_set_tile_cfg(0, 1, 32, 1, 0)
+    with pytest.raises(cs.ConvError):
+        cs.conv_get_tile_cfg(4, 0)
+    cs.conv_set_tile_cfg(2, 1, 48, 2, 6)
+    c = cs.conv_get_tile_cfg(2, 1)
+    assert (c.rows_per_tile, c.waves_per_wg, c.persist_wgs_per_cu) == (48, 2, 6)
+    cs.conv_set_tile_cfg(0, 0, before.rows_per_tile, before.waves_per_wg)
+    assert cs.conv_get_tile_cfg(0, 0).as_dict() == before.as_dict()
+
+
+def test_serve_config_validation():
+    L = cs.lib()
+    h = ctypes.c_void_p()
+    for cfg in (cs.conv_serve_cfg(0, 4, 2, 8, -1), cs.conv_serve_cfg(1 << 30, 0, 2, 8, -1),
+                cs.conv_serve_cfg(1 << 30, 4, 0, 8, -1), cs.conv_serve_cfg(1 << 30, 4, 17, 8, -1),
+                cs.conv_serve_cfg(1 << 30, 4, 2, 0, -1)):
+        assert L.conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == cs.CONV_EINVAL
+    assert L.conv_serve_poll(None, 1, None) == cs.CONV_EINVAL
+    assert L.conv_serve_destroy(None) == cs.CONV_OK
+
+
+def test_tuner_validation():
+    L = cs.lib()
+    best = cs.conv_tile_cfg()
+    assert L.conv_tune(2, 1, None, None, None, None, 1, None, ctypes.byref(best),
+                       None) == cs.CONV_EINVAL
+    assert L.conv_tune(0, 0, None, None, None, None, 1, None, ctypes.byref(best),
+                       None) == cs.CONV_EINVAL
+
+
+def test_binding_describes_tensors():
+    import torch
+
+    t = torch.zeros(3, 10, 12)
+    i = cs.image_of(t)
+    assert (i.planes, i.rows, i.cols, i.dtype, i.pitch, i.plane_stride) == (3, 10, 12, 0, 12, 120)
+    big = torch.zeros(3, 12, 20, dtype=torch.bfloat16)
+    v = big[:, 1:11, 2:14]
+    i = cs.image_of(v)
+    assert (i.planes, i.rows, i.cols, i.dtype, i.pitch, i.plane_stride) == (3, 10, 12, 2, 20, 240)
+    with pytest.raises(TypeError):
+        cs.image_of(torch.zeros(2, 2, 2, dtype=torch.float64))
