@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 P, R, C = 3, 4096, 4096
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1711_09791_amd", "csrc", "conv_kernels.hip")
+KERNEL_DIR = os.path.join(ROOT, "paper_1711_09791_amd", "csrc")
 
 
 def parse():
@@ -47,8 +47,13 @@ def parse():
 
 
 def kernel_src_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the device-code sources (conv_kernels*.{h,hip}, conv_internal.h)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_DIR)):
+        if name.startswith("conv_kernels") or name == "conv_internal.h":
+            with open(os.path.join(KERNEL_DIR, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
 def traffic_for(form: str):

@@ -217,11 +217,15 @@ typedef struct conv_server conv_server;
 
 conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv);
 /* Non-blocking.  d_in/d_out: device image (FP32/FP16/BF16) as in
- * conv_sep5_1pass; k: 5 host taps.  Footprint larger than the budget ->
- * CONV_ENOMEM; bad arguments -> CONV_EINVAL / CONV_EALIAS.  *ticket > 0. */
+ * conv_sep5_1pass; k: 5 host taps.  `stream` is the caller's producer stream
+ * (NULL: the default stream): work enqueued on it before this call -- the
+ * writes that fill d_in, say -- completes before the request's kernel starts
+ * (an event is recorded on it here and waited on by the launch).  Footprint
+ * larger than the budget -> CONV_ENOMEM; bad arguments -> CONV_EINVAL /
+ * CONV_EALIAS.  *ticket > 0. */
 conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out,
                               const float k[5], const conv_image *img,
-                              uint64_t *ticket);
+                              hipStream_t stream, uint64_t *ticket);
 /* CONV_OK: done (times filled if t != NULL; the ticket is then forgotten);
  * CONV_EAGAIN: pending; CONV_ENOTFOUND: unknown ticket; CONV_EHIP: its launch
  * failed. */

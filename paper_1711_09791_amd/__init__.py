@@ -113,7 +113,7 @@ def lib():
         "conv_tune": [i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, i32, vp, cfgp,
                       fp],
         "conv_serve_create": [ctypes.POINTER(conv_serve_cfg), ctypes.POINTER(vp)],
-        "conv_serve_submit": [vp, vp, vp, fp, imgp, ctypes.POINTER(u64)],
+        "conv_serve_submit": [vp, vp, vp, fp, imgp, vp, ctypes.POINTER(u64)],
         "conv_serve_poll": [vp, u64, ctypes.POINTER(conv_req_times)],
         "conv_serve_drain": [vp],
         "conv_serve_destroy": [vp],
@@ -171,6 +171,20 @@ def image_of(t) -> conv_image:
                       int(sp) if P > 1 else 0)
 
 
+def _same_layout(a, b, what: str = "output") -> None:
+    """The C ABI describes input and output with ONE descriptor: a tensor pair
+    must agree in shape, dtype, device and strides (raw pointers are the
+    caller's responsibility)."""
+    if isinstance(a, int) or isinstance(b, int) or a is None or b is None:
+        return
+    if tuple(a.shape) != tuple(b.shape) or a.dtype != b.dtype or a.device != b.device:
+        raise ValueError(f"{what} must match the input's shape, dtype and device "
+                         f"({tuple(b.shape)} {b.dtype} vs {tuple(a.shape)} {a.dtype})")
+    if a.numel() and tuple(a.stride()) != tuple(b.stride()):
+        raise ValueError(f"{what} strides {tuple(b.stride())} differ from the input's "
+                         f"{tuple(a.stride())}; both share one layout descriptor")
+
+
 def _taps(k) -> ctypes.Array:
     vals = [float(v) for v in (k.tolist() if hasattr(k, "tolist") else k)]
     if len(vals) != 5:
@@ -200,7 +214,9 @@ def _ptr(x):
 
 def conv_sep5_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, stream=None):
     """Two-pass form: row kernel into the FP32 workspace, then column kernel."""
-    img = img or image_of(d_in)
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
     return _check(lib().conv_sep5_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
                                         ctypes.byref(img), _stream(stream)))
 
@@ -208,7 +224,9 @@ def conv_sep5_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, s
 def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
                     img: conv_image | None = None, stream=None):
     """Single-pass form (fused row+column, or the direct 25-tap mode)."""
-    img = img or image_of(d_in)
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
     return _check(lib().conv_sep5_1pass(_ptr(d_in), _ptr(d_out), _taps(k), ctypes.byref(img),
                                         int(mode), _stream(stream)))
 
@@ -217,7 +235,11 @@ def _batch_args(ins, outs, ks, imgs):
     n = len(ins)
     if len(outs) != n or len(ks) != n:
         raise ValueError("ins, outs and ks must have the same length")
-    imgs = list(imgs) if imgs is not None else [image_of(t) for t in ins]
+    if imgs is None:
+        for i, (a, b) in enumerate(zip(ins, outs)):
+            _same_layout(a, b, f"output {i}")
+        imgs = [image_of(t) for t in ins]
+    imgs = list(imgs)
     pin = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in ins])
     pout = (ctypes.c_void_p * max(n, 1))(*[_ptr(t).value for t in outs])
     flat = []
@@ -298,11 +320,15 @@ class Server:
         _check(lib().conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
 
-    def submit(self, d_in, d_out, k, img: conv_image | None = None) -> int:
-        img = img or image_of(d_in)
+    def submit(self, d_in, d_out, k, img: conv_image | None = None, stream=None) -> int:
+        """Queue one request.  Work already enqueued on `stream` (default: torch's
+        current stream) completes before the request's kernel starts."""
+        if img is None:
+            _same_layout(d_in, d_out)
+            img = image_of(d_in)
         t = ctypes.c_uint64()
         _check(lib().conv_serve_submit(self._h, _ptr(d_in), _ptr(d_out), _taps(k),
-                                       ctypes.byref(img), ctypes.byref(t)))
+                                       ctypes.byref(img), _stream(stream), ctypes.byref(t)))
         return int(t.value)
 
     def poll(self, ticket: int):
@@ -339,8 +365,8 @@ def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int
     return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device)
 
 
-def conv_serve_submit(srv: Server, d_in, d_out, k, img=None) -> int:
-    return srv.submit(d_in, d_out, k, img)
+def conv_serve_submit(srv: Server, d_in, d_out, k, img=None, stream=None) -> int:
+    return srv.submit(d_in, d_out, k, img, stream)
 
 
 def conv_serve_poll(srv: Server, ticket: int):

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libconvsep5.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["conv_kernels.hip", "conv_api.cpp", "conv_tune.cpp", "conv_serve.cpp"]
+SOURCES = ["conv_kernels_f32.hip", "conv_kernels_f16.hip", "conv_kernels_bf16.hip",
+           "conv_api.cpp", "conv_tune.cpp", "conv_serve.cpp"]
 ARCH = "gfx950"
 
 COMMON = [
@@ -52,7 +53,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libconvsep5.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]

@@ -84,10 +84,12 @@ bool overlaps(const void *a, int64_t na, const void *b, int64_t nb) {
 
 // ---- tile configuration ---------------------------------------------------------
 static std::mutex g_cfg_mu;
+// Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image; the
+// 64-image uneven batch); conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][2] = {
-    {{32, 4, 0}, {64, 1, 8}},
-    {{32, 4, 0}, {64, 1, 8}},
-    {{32, 4, 0}, {64, 1, 8}},
+    {{8, 2, 0}, {16, 1, 8}},
+    {{32, 4, 0}, {16, 1, 8}},
+    {{32, 4, 0}, {16, 1, 8}},
 };
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
@@ -299,7 +301,7 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
     const int64_t cap = (int64_t)st->cus * cfg.persist_wgs_per_cu;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
     hipError_t e = launch_batch((const ImgDev *)slot->dev, (int)descs.size(), total, dtype, mode,
-                                cfg.waves_per_wg, grid, s);
+                                cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
     rc = finish_slot(slot, s);
     if (e != hipSuccess) return hip_error(e, "batch kernel launch");
     return rc;
@@ -460,7 +462,7 @@ conv_status conv_batch_plan_create(int32_t n, const void *const *d_in, void *con
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, capn));
             le = launch_batch(p->d_descs, (int)descs.size(), total, dtype,
                               mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
-                              cfg.waves_per_wg, grid, p->cap);
+                              cfg.waves_per_wg, cfg.rows_per_tile, grid, p->cap);
         }
         e = hipStreamEndCapture(p->cap, &p->graph);
     }

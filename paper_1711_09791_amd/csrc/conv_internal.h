@@ -45,11 +45,31 @@ struct ImgDev {
 inline int vec_of(int dtype) { return dtype == 0 ? 4 : 8; }
 inline int esize_of(int dtype) { return dtype == 0 ? 4 : 2; }
 
-// Kernel launchers (conv_kernels.hip).  `waves` is 1, 2 or 4.
-hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves,
-                        int64_t nblocks, hipStream_t s);
-hipError_t launch_batch(const ImgDev *d_descs, int n, int64_t total_tiles,
-                        int dtype, int mode, int waves, int grid,
-                        hipStream_t s);
+// Kernel launchers, one translation unit per storage type
+// (conv_kernels_{f32,f16,bf16}.hip).  `waves` is 1, 2 or 4; bands of 4 or 8
+// rows (im.th / th) select the fully unrolled band kernels.
+hipError_t launch_image_f32(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s);
+hipError_t launch_image_f16(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s);
+hipError_t launch_image_bf16(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s);
+hipError_t launch_batch_f32(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
+                            int grid, hipStream_t s);
+hipError_t launch_batch_f16(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
+                            int grid, hipStream_t s);
+hipError_t launch_batch_bf16(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
+                             int grid, hipStream_t s);
+
+inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
+                               hipStream_t s) {
+    return dtype == 0 ? launch_image_f32(im, mode, waves, nblocks, s)
+         : dtype == 1 ? launch_image_f16(im, mode, waves, nblocks, s)
+                      : launch_image_bf16(im, mode, waves, nblocks, s);
+}
+
+inline hipError_t launch_batch(const ImgDev *d, int n, int64_t total, int dtype, int mode,
+                               int waves, int th, int grid, hipStream_t s) {
+    return dtype == 0 ? launch_batch_f32(d, n, total, mode, waves, th, grid, s)
+         : dtype == 1 ? launch_batch_f16(d, n, total, mode, waves, th, grid, s)
+                      : launch_batch_bf16(d, n, total, mode, waves, th, grid, s);
+}
 
 }  // namespace convsep5

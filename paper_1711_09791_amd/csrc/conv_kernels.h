@@ -1,4 +1,5 @@
-// conv_kernels.hip -- gfx950 kernels of the width-5 separable convolution.
+// conv_kernels.h -- gfx950 kernels of the width-5 separable convolution
+// (templates; instantiated per storage type by conv_kernels_{f32,f16,bf16}.hip).
 //
 // Operation: Eq. 1 of arXiv 1711.09791 (Section 1) with K[i][j] = k_i k_j,
 // correlation form, computed on pixels whose 5x5 neighbourhood is inside the
@@ -9,14 +10,22 @@
 //     8 FP16/BF16), so one wavefront row access is 1 KiB of contiguous,
 //     fully coalesced memory;
 //   * a tile is a column strip of 64*VEC columns times a band of `th` output
-//     rows of one plane; the wavefront walks down the band row by row;
+//     rows of one plane.  Tiles are numbered strip-fastest (plane, band,
+//     strip group), so the waves resident at any moment cover whole image
+//     rows of a compact window that sweeps down the image (DRAM page
+//     locality); with the round-robin workgroup-to-XCD dispatch, a column
+//     strip then stays on one XCD whenever the strip-group count is a
+//     multiple of 8, so the halo rows shared by vertically adjacent bands
+//     meet in that XCD's L2;
+//   * bands of 4 or 8 rows are fully unrolled: all th+4 input rows are
+//     loaded before the first is used; other heights walk down the band
+//     with a 5-row prefetch ring;
 //   * horizontal neighbours come from the adjacent lanes through DPP
 //     wave_shr:1 / wave_shl:1 moves; lane 0 and lane 63 fetch the 2-column
 //     halo outside the strip themselves;
 //   * the vertical 5-row window (row-filtered rows, or raw rows for the
-//     direct form) lives in VGPRs and rotates through five register slots
-//     with no moves (the loop is unrolled by 5);
-//   * input rows are prefetched 5 rows ahead into a ring of raw registers;
+//     direct form) lives in VGPRs; in the walking form it rotates through
+//     five register slots with no moves (the loop is unrolled by 5);
 //   * all global accesses are raw buffer instructions on a per-row buffer
 //     resource whose size is the row's byte length: lanes past the right
 //     edge read 0 and their stores are dropped by the hardware range check,
@@ -28,6 +37,8 @@
 //   direct25    p_a = chain over the 5 taps of kernel row a with K[a][b];
 //               o = ((p_0 + p_1) + (p_2 + p_3)) + p_4
 // Built with -ffp-contract=off so that nothing else is fused.
+#pragma once
+
 #include "conv_internal.h"
 
 #include <type_traits>
@@ -55,15 +66,21 @@ __device__ __forceinline__ float dec(F16, uint32_t b) {
 __device__ __forceinline__ float dec(BF16, uint32_t b) { return __uint_as_float(b << 16); }
 
 __device__ __forceinline__ uint32_t enc(F32, float f) { return __float_as_uint(f); }
-__device__ __forceinline__ uint32_t enc(F16, float f) {
-    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);  // v_cvt_f16_f32, RNE
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+// Two FP32 values -> one packed word of two 16-bit values (low half = a),
+// rounded to nearest even by the hardware converters (v_cvt_pk_f16_f32 /
+// v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint32_t enc2(F16, float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, h2v));
 }
-__device__ __forceinline__ uint32_t enc(BF16, float f) {   // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+__device__ __forceinline__ uint32_t enc2(BF16, float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, b2v));
 }
+__device__ __forceinline__ uint32_t enc(F16, float f) { return enc2(F16{}, f, 0.0f) & 0xffffu; }
+__device__ __forceinline__ uint32_t enc(BF16, float f) { return enc2(BF16{}, f, 0.0f) & 0xffffu; }
 
 // ---- buffer resources, DPP ----------------------------------------------
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
@@ -200,8 +217,7 @@ __device__ __forceinline__ void store_out(char *row, uint32_t rbytes, int x,
             q = u4{enc(D{}, o[0]), enc(D{}, o[1]), enc(D{}, o[2]), enc(D{}, o[3])};
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                q[i] = enc(D{}, o[2 * i]) | (enc(D{}, o[2 * i + 1]) << 16);
+            for (int i = 0; i < 4; ++i) q[i] = enc2(D{}, o[2 * i], o[2 * i + 1]);
         }
         __builtin_amdgcn_raw_buffer_store_b128(q, rs, x * D::ESZ, 0, NT);
     } else {
@@ -273,49 +289,60 @@ __device__ __forceinline__ void direct25(const float (&r0)[N + 4], const float (
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// ---- one band of a vertical-filter kernel (fused, direct25, column pass) ----
-template <class D, bool AL, int MODE>
-__device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int xs, int y0, int y1,
-                                              int lane) {
-    constexpr int VEC = D::VEC;
-    constexpr bool DIRECT = MODE == MODE_DIRECT25;
-    constexpr bool COL = MODE == MODE_COLPASS;
-    constexpr int WN = DIRECT ? VEC + 4 : VEC;
+
+// ---- per-band context of the vertical-filter kernels -------------------------
+// (fused, direct25 and the two-pass column kernel)
+// EDGE = false: the tile touches no border row or column, so no output of it
+// needs the zero frame and the selects are compiled out.
+template <class D, bool AL, int MODE, bool EDGE>
+struct VBand {
+    static constexpr int VEC = D::VEC;
+    static constexpr bool DIRECT = MODE == MODE_DIRECT25;
+    static constexpr bool COL = MODE == MODE_COLPASS;
+    static constexpr int WN = DIRECT ? VEC + 4 : VEC;  // floats per window row
     using RawIn = typename std::conditional<COL, RawT<VEC, AL>, Raw<D, AL>>::type;
 
-    const int H = im.rows, W = im.cols;
-    const int x = xs + lane * VEC;
+    const ImgDev &im;
+    int H, W, x, hoff;
     const char *sbase;
     int64_t sstride;
     uint32_t sbytes;
-    if constexpr (COL) {
-        sbase = (const char *)(im.tmp + (int64_t)plane * H * W);
-        sstride = (int64_t)W * 4;
-        sbytes = (uint32_t)W * 4;
-    } else {
-        sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
-        sstride = im.pitch * D::ESZ;
-        sbytes = (uint32_t)W * D::ESZ;
-    }
-    char *dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
-    const int64_t dstride = im.pitch * D::ESZ;
-    const uint32_t dbytes = (uint32_t)W * D::ESZ;
-    const int hl = xs - 2, hr = xs + WAVE * VEC;
-    const int hoff = lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
-                               : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
+    char *dbase;
+    int64_t dstride;
+    uint32_t dbytes;
     bool cm[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
-    const int rlim = min(y1 + 1, H - 1);
 
-    auto fetch = [&](RawIn &r, int row) {
-        const char *p = sbase + (int64_t)clampi(row, 0, rlim) * sstride;
+    __device__ __forceinline__ VBand(const ImgDev &im_, int plane, int xs, int lane) : im(im_) {
+        H = im.rows;
+        W = im.cols;
+        x = xs + lane * VEC;
+        if constexpr (COL) {
+            sbase = (const char *)(im.tmp + (int64_t)plane * H * W);
+            sstride = (int64_t)W * 4;
+            sbytes = (uint32_t)W * 4;
+        } else {
+            sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+            sstride = im.pitch * D::ESZ;
+            sbytes = (uint32_t)W * D::ESZ;
+        }
+        dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
+        dstride = im.pitch * D::ESZ;
+        dbytes = (uint32_t)W * D::ESZ;
+        const int hl = xs - 2, hr = xs + WAVE * VEC;
+        hoff = lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
+                         : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
+    }
+    // `row` must already lie in [0, H)
+    __device__ __forceinline__ void fetch(RawIn &r, int row) const {
+        const char *p = sbase + (int64_t)row * sstride;
         if constexpr (COL)
             issue_t<VEC, AL>(r, p, sbytes, x);
         else
             issue<D>(r, p, sbytes, x, hoff);
-    };
-    auto produce = [&](const RawIn &r, float (&w)[WN]) {
+    }
+    __device__ __forceinline__ void produce(const RawIn &r, float (&w)[WN]) const {
         if constexpr (COL) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) w[e] = __uint_as_float(r.w[e]);
@@ -326,32 +353,65 @@ __device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int x
             decode<D>(r, v);
             hfilter<VEC>(v, im.tp.k, w);
         }
-    };
-    auto emit = [&](int y, const float (&a)[WN], const float (&b)[WN], const float (&c)[WN],
-                    const float (&d)[WN], const float (&e)[WN]) {
+    }
+    // Output row y from window rows y-2 .. y+2.
+    __device__ __forceinline__ void emit(int y, const float (&a)[WN], const float (&b)[WN],
+                                         const float (&c)[WN], const float (&d)[WN],
+                                         const float (&e)[WN]) const {
         float o[VEC];
         if constexpr (DIRECT)
             direct25<VEC>(a, b, c, d, e, im.tp.K, o);
         else
             vfilter<VEC>(a, b, c, d, e, im.tp.k, o);
-        const bool vr = (y >= 2) && (y < H - 2);
+        if constexpr (EDGE) {
+            const bool vr = (y >= 2) && (y < H - 2);
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) o[i] = (vr && cm[i]) ? o[i] : 0.0f;
+            for (int i = 0; i < VEC; ++i) o[i] = (vr && cm[i]) ? o[i] : 0.0f;
+        }
         store_out<D, AL>(dbase + (int64_t)y * dstride, dbytes, x, o);
-    };
+    }
+};
 
-    float w[5][WN];
-    RawIn ring[5];
+// Band of compile-time height TH: all TH+4 input rows are issued first.
+// Rows outside [0, H) are clamped; they only feed border outputs (y < 2 or
+// y >= H-2), which are written as zeros.
+template <class D, bool AL, int MODE, bool EDGE, int TH>
+__device__ __forceinline__ void band_vertical_fixed(const ImgDev &im, int plane, int xs, int y0,
+                                                    int lane) {
+    using B = VBand<D, AL, MODE, EDGE>;
+    const B b(im, plane, xs, lane);
+    const int Hm1 = b.H - 1;
+    typename B::RawIn raw[TH + 4];
+#pragma unroll
+    for (int i = 0; i < TH + 4; ++i) b.fetch(raw[i], clampi(y0 - 2 + i, 0, Hm1));
+    float w[TH + 4][B::WN];
+#pragma unroll
+    for (int i = 0; i < TH + 4; ++i) b.produce(raw[i], w[i]);
+#pragma unroll
+    for (int j = 0; j < TH; ++j) b.emit(y0 + j, w[j], w[j + 1], w[j + 2], w[j + 3], w[j + 4]);
+}
+
+// Band of any height: walk down with a 5-row window and a 5-row prefetch ring.
+template <class D, bool AL, int MODE, bool EDGE>
+__device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int xs, int y0, int y1,
+                                              int lane) {
+    using B = VBand<D, AL, MODE, EDGE>;
+    const B b(im, plane, xs, lane);
+    const int rlim = min(y1 + 1, b.H - 1);
+    auto fetch = [&](typename B::RawIn &r, int row) { b.fetch(r, clampi(row, 0, rlim)); };
+
+    float w[5][B::WN];
+    typename B::RawIn ring[5];
     {
-        RawIn p0, p1, p2, p3;
+        typename B::RawIn p0, p1, p2, p3;
         fetch(p0, y0 - 2);
         fetch(p1, y0 - 1);
         fetch(p2, y0);
         fetch(p3, y0 + 1);
-        produce(p0, w[0]);
-        produce(p1, w[1]);
-        produce(p2, w[2]);
-        produce(p3, w[3]);
+        b.produce(p0, w[0]);
+        b.produce(p1, w[1]);
+        b.produce(p2, w[2]);
+        b.produce(p3, w[3]);
     }
     fetch(ring[4], y0 + 2);
     fetch(ring[0], y0 + 3);
@@ -363,13 +423,13 @@ __device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int x
     // Output row y: slot S holds row y+2 (just produced), (S+4)%5 row y+1,
     // (S+3)%5 row y, (S+2)%5 row y-1, (S+1)%5 row y-2.  ring[S] holds row
     // y+2 on entry and is refilled with row y+7.
-#define CONV_VSTEP(S)                                                                   \
-    {                                                                                    \
-        produce(ring[S], w[S]);                                                          \
-        fetch(ring[S], y + 7);                                                           \
-        emit(y, w[((S) + 1) % 5], w[((S) + 2) % 5], w[((S) + 3) % 5], w[((S) + 4) % 5], \
-             w[S]);                                                                      \
-        ++y;                                                                             \
+#define CONV_VSTEP(S)                                                                     \
+    {                                                                                      \
+        b.produce(ring[S], w[S]);                                                          \
+        fetch(ring[S], y + 7);                                                             \
+        b.emit(y, w[((S) + 1) % 5], w[((S) + 2) % 5], w[((S) + 3) % 5], w[((S) + 4) % 5], \
+               w[S]);                                                                      \
+        ++y;                                                                               \
     }
     while (y + 5 <= y1) {
         CONV_VSTEP(4) CONV_VSTEP(0) CONV_VSTEP(1) CONV_VSTEP(2) CONV_VSTEP(3)
@@ -387,46 +447,77 @@ __device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int x
 #undef CONV_VSTEP
 }
 
-// ---- one band of the two-pass row kernel -------------------------------------
-template <class D, bool AL>
+// ---- the two-pass row kernel -----------------------------------------------------
+template <class D, bool AL, bool EDGE>
+struct RBand {
+    static constexpr int VEC = D::VEC;
+    const ImgDev &im;
+    int x, hoff;
+    const char *sbase;
+    int64_t sstride;
+    uint32_t sbytes;
+    char *tbase;
+    int64_t tstride;
+    uint32_t tbytes;
+    bool cm[VEC];
+
+    __device__ __forceinline__ RBand(const ImgDev &im_, int plane, int xs, int lane) : im(im_) {
+        const int H = im.rows, W = im.cols;
+        x = xs + lane * VEC;
+        sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+        sstride = im.pitch * D::ESZ;
+        sbytes = (uint32_t)W * D::ESZ;
+        tbase = (char *)(im.tmp + (int64_t)plane * H * W);
+        tstride = (int64_t)W * 4;
+        tbytes = (uint32_t)W * 4;
+        const int hl = xs - 2, hr = xs + WAVE * VEC;
+        hoff = lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
+                         : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
+    }
+    __device__ __forceinline__ void fetch(Raw<D, AL> &r, int row) const {
+        issue<D>(r, sbase + (int64_t)row * sstride, sbytes, x, hoff);
+    }
+    // T[row] = horizontal filter on columns 2..W-3, 0 elsewhere.
+    __device__ __forceinline__ void filter_store(const Raw<D, AL> &r, int row) const {
+        float v[VEC + 4], h[VEC];
+        decode<D>(r, v);
+        hfilter<VEC>(v, im.tp.k, h);
+        if constexpr (EDGE) {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) h[i] = cm[i] ? h[i] : 0.0f;
+        }
+        store_t<VEC, AL>(tbase + (int64_t)row * tstride, tbytes, x, h);
+    }
+};
+
+template <class D, bool AL, bool EDGE, int TH>
+__device__ __forceinline__ void band_rowpass_fixed(const ImgDev &im, int plane, int xs, int y0,
+                                                   int lane) {
+    const RBand<D, AL, EDGE> b(im, plane, xs, lane);
+    Raw<D, AL> raw[TH];
+#pragma unroll
+    for (int i = 0; i < TH; ++i) b.fetch(raw[i], y0 + i);
+#pragma unroll
+    for (int i = 0; i < TH; ++i) b.filter_store(raw[i], y0 + i);
+}
+
+template <class D, bool AL, bool EDGE>
 __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs, int y0, int y1,
                                              int lane) {
-    constexpr int VEC = D::VEC;
-    const int H = im.rows, W = im.cols;
-    const int x = xs + lane * VEC;
-    const char *sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
-    const int64_t sstride = im.pitch * D::ESZ;
-    const uint32_t sbytes = (uint32_t)W * D::ESZ;
-    char *tbase = (char *)(im.tmp + (int64_t)plane * H * W);
-    const int64_t tstride = (int64_t)W * 4;
-    const uint32_t tbytes = (uint32_t)W * 4;
-    const int hl = xs - 2, hr = xs + WAVE * VEC;
-    const int hoff = lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
-                               : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
-    bool cm[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
+    const RBand<D, AL, EDGE> b(im, plane, xs, lane);
     const int rlim = y1 - 1;
-
-    auto fetch = [&](Raw<D, AL> &r, int row) {
-        issue<D>(r, sbase + (int64_t)min(row, rlim) * sstride, sbytes, x, hoff);
-    };
     Raw<D, AL> ring[5];
-    fetch(ring[0], y0);
-    fetch(ring[1], y0 + 1);
-    fetch(ring[2], y0 + 2);
-    fetch(ring[3], y0 + 3);
-    fetch(ring[4], y0 + 4);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) b.fetch(ring[i], min(y0 + i, rlim));
     int y = y0;
-#define CONV_RSTEP(S)                                                   \
-    {                                                                    \
-        float v[VEC + 4], h[VEC];                                        \
-        decode<D>(ring[S], v);                                           \
-        fetch(ring[S], y + 5);                                           \
-        hfilter<VEC>(v, im.tp.k, h);                                     \
-        _Pragma("unroll") for (int i = 0; i < VEC; ++i) h[i] = cm[i] ? h[i] : 0.0f; \
-        store_t<VEC, AL>(tbase + (int64_t)y * tstride, tbytes, x, h);    \
-        ++y;                                                             \
+#define CONV_RSTEP(S)                                 \
+    {                                                  \
+        const Raw<D, AL> cur = ring[S];                \
+        b.fetch(ring[S], min(y + 5, rlim));            \
+        b.filter_store(cur, y);                        \
+        ++y;                                           \
     }
     while (y + 5 <= y1) {
         CONV_RSTEP(0) CONV_RSTEP(1) CONV_RSTEP(2) CONV_RSTEP(3) CONV_RSTEP(4)
@@ -444,89 +535,104 @@ __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs
 #undef CONV_RSTEP
 }
 
-// ---- tiles -----------------------------------------------------------------
-// Logical tile lt = (plane, strip group, band), band fastest.  Wave `wave` of
-// the workgroup takes strip sg*WAVES + wave of the group.
-template <class D, bool AL, int MODE, int WAVES>
+// ---- tiles -----------------------------------------------------------------------
+// Logical tile lt = (plane, band, strip group), strip group fastest.  Wave
+// `wave` of the workgroup takes strip sg*WAVES + wave of the group.  TH > 0:
+// full bands of TH rows use the unrolled form (the host then sets th = TH).
+template <class D, bool AL, int MODE, bool EDGE, int TH>
+__device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, int y0, int y1,
+                                         int lane) {
+    if constexpr (MODE == MODE_ROWPASS) {
+        if constexpr (TH > 0) {
+            if (y1 - y0 == TH) {
+                band_rowpass_fixed<D, AL, EDGE, TH>(im, plane, xs, y0, lane);
+                return;
+            }
+        }
+        band_rowpass<D, AL, EDGE>(im, plane, xs, y0, y1, lane);
+    } else {
+        if constexpr (TH > 0) {
+            if (y1 - y0 == TH) {
+                band_vertical_fixed<D, AL, MODE, EDGE, TH>(im, plane, xs, y0, lane);
+                return;
+            }
+        }
+        band_vertical<D, AL, MODE, EDGE>(im, plane, xs, y0, y1, lane);
+    }
+}
+
+template <class D, bool AL, int MODE, int WAVES, int TH>
 __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave, int lane) {
-    const int64_t per_plane = (int64_t)im.nsg * im.nb;
-    const int plane = (int)(lt / per_plane);
-    const int64_t rem = lt - (int64_t)plane * per_plane;
-    const int sg = (int)(rem / im.nb);
-    const int band = (int)(rem - (int64_t)sg * im.nb);
+    const int sg = (int)(lt % im.nsg);
+    const int64_t t = lt / im.nsg;
+    const int band = (int)(t % im.nb);
+    const int plane = (int)(t / im.nb);
     const int strip = sg * WAVES + wave;
     if (strip >= im.ns) return;
     const int xs = strip * (WAVE * D::VEC);
     const int y0 = band * im.th;
     const int y1 = min(y0 + im.th, im.rows);
-    if constexpr (MODE == MODE_ROWPASS)
-        band_rowpass<D, AL>(im, plane, xs, y0, y1, lane);
+    // Does any output of this tile lie in the 2-pixel frame?  (The row pass
+    // writes every row, so only columns matter there.)
+    const bool col_edge = xs < 2 || xs + WAVE * D::VEC > im.cols - 2;
+    const bool row_edge = MODE != MODE_ROWPASS && (y0 < 2 || y1 > im.rows - 2);
+    if (col_edge || row_edge)
+        run_band<D, AL, MODE, true, TH>(im, plane, xs, y0, y1, lane);
     else
-        band_vertical<D, AL, MODE>(im, plane, xs, y0, y1, lane);
+        run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
 }
 
-// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8).
-// Renumber them so that each XCD gets one contiguous run of logical blocks:
-// vertically adjacent bands, which share halo rows, then meet in one L2.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-    constexpr int X = 8;
-    const int q = n / X, r = n % X;
-    const int xcd = b % X, i = b / X;
-    return xcd * q + min(xcd, r) + i;
-}
-
-template <class D, bool AL, int MODE, int WAVES>
+// One workgroup per logical tile, in launch order (so the resident waves
+// sweep the image row-band by row-band); grids above 2^20 workgroups loop.
+template <class D, bool AL, int MODE, int WAVES, int TH>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (int64_t base = 0; base < nblocks; base += gridDim.x) {
-        const int64_t left = nblocks - base;
-        const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
-        if ((int)blockIdx.x >= cnt) break;
-        run_tile<D, AL, MODE, WAVES>(im, base + xcd_remap(blockIdx.x, cnt), wave, lane);
-    }
+    for (int64_t lt = blockIdx.x; lt < nblocks; lt += gridDim.x)
+        run_tile<D, AL, MODE, WAVES, TH>(im, lt, wave, lane);
 }
 
-// Persistent batch kernel: the grid is a fixed multiple of the CU count; each
-// workgroup takes one contiguous run of the launch's tiles (images in order,
-// then plane, strip group, band), finds the image owning each tile from the
-// descriptor table's tile ranges, and runs it.
-template <class D, int MODE, int WAVES>
+// Persistent batch kernel: a fixed grid (a multiple of the CU count) strides
+// over the launch's tiles (images in order, then plane, band, strip group),
+// so the resident workgroups always work on one compact window of the batch.
+// The owning image of each tile is found by advancing through the descriptor
+// table's tile ranges (tiles only increase within a workgroup).
+template <class D, int MODE, int WAVES, int TH>
 __global__ __launch_bounds__(WAVE *WAVES) void k_batch(const ImgDev *__restrict__ descs, int n,
                                                        int64_t total) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int G = gridDim.x;
-    const int64_t L = xcd_remap(blockIdx.x, G);
-    const int64_t t0 = total * L / G, t1 = total * (L + 1) / G;
-    if (t0 >= t1) return;
-    int lo = 0, hi = n - 1;  // last image whose first tile is <= t0
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].tile_begin <= t0) lo = mid;
-        else hi = mid - 1;
-    }
-    int i = lo;
-    for (int64_t t = t0; t < t1; ++t) {
-        while (t >= descs[i].tile_end) ++i;
+    int i = 0;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        while (i < n - 1 && t >= descs[i].tile_end) ++i;
         const ImgDev &im = descs[i];
         if (im.aligned)
-            run_tile<D, true, MODE, WAVES>(im, t - im.tile_begin, wave, lane);
+            run_tile<D, true, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);
         else
-            run_tile<D, false, MODE, WAVES>(im, t - im.tile_begin, wave, lane);
+            run_tile<D, false, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);
     }
 }
 
-// ---- dispatch ----------------------------------------------------------------
-template <class D, bool AL, int MODE>
-hipError_t launch_image_w(const ImgDev &im, int waves, int64_t nblocks, hipStream_t s) {
+// ---- launchers -------------------------------------------------------------------
+template <class D, bool AL, int MODE, int WAVES>
+hipError_t launch_image_th(const ImgDev &im, int64_t nblocks, hipStream_t s) {
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
-    switch (waves) {
-    case 1: hipLaunchKernelGGL((k_image<D, AL, MODE, 1>), dim3(grid), dim3(WAVE), 0, s, im, nblocks); break;
-    case 2: hipLaunchKernelGGL((k_image<D, AL, MODE, 2>), dim3(grid), dim3(2 * WAVE), 0, s, im, nblocks); break;
-    default: hipLaunchKernelGGL((k_image<D, AL, MODE, 4>), dim3(grid), dim3(4 * WAVE), 0, s, im, nblocks); break;
+    const dim3 blk(WAVE * WAVES);
+    switch (im.th) {
+    case 4: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4>), dim3(grid), blk, 0, s, im, nblocks); break;
+    case 8: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8>), dim3(grid), blk, 0, s, im, nblocks); break;
+    default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0>), dim3(grid), blk, 0, s, im, nblocks); break;
     }
     return hipGetLastError();
+}
+
+template <class D, bool AL, int MODE>
+hipError_t launch_image_w(const ImgDev &im, int waves, int64_t nblocks, hipStream_t s) {
+    switch (waves) {
+    case 1: return launch_image_th<D, AL, MODE, 1>(im, nblocks, s);
+    case 2: return launch_image_th<D, AL, MODE, 2>(im, nblocks, s);
+    default: return launch_image_th<D, AL, MODE, 4>(im, nblocks, s);
+    }
 }
 
 template <class D, bool AL>
@@ -540,47 +646,39 @@ hipError_t launch_image_m(const ImgDev &im, int mode, int waves, int64_t nblocks
 }
 
 template <class D>
-hipError_t launch_image_a(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s) {
+hipError_t launch_image_t(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s) {
     return im.aligned ? launch_image_m<D, true>(im, mode, waves, nblocks, s)
                       : launch_image_m<D, false>(im, mode, waves, nblocks, s);
 }
 
-template <class D, int MODE>
-hipError_t launch_batch_w(const ImgDev *d, int n, int64_t total, int waves, int grid,
-                          hipStream_t s) {
-    switch (waves) {
-    case 1: hipLaunchKernelGGL((k_batch<D, MODE, 1>), dim3(grid), dim3(WAVE), 0, s, d, n, total); break;
-    case 2: hipLaunchKernelGGL((k_batch<D, MODE, 2>), dim3(grid), dim3(2 * WAVE), 0, s, d, n, total); break;
-    default: hipLaunchKernelGGL((k_batch<D, MODE, 4>), dim3(grid), dim3(4 * WAVE), 0, s, d, n, total); break;
+template <class D, int MODE, int WAVES>
+hipError_t launch_batch_th(const ImgDev *d, int n, int64_t total, int th, int grid, hipStream_t s) {
+    const dim3 blk(WAVE * WAVES);
+    switch (th) {
+    case 4: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 4>), dim3(grid), blk, 0, s, d, n, total); break;
+    case 8: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 8>), dim3(grid), blk, 0, s, d, n, total); break;
+    default: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 0>), dim3(grid), blk, 0, s, d, n, total); break;
     }
     return hipGetLastError();
 }
 
-template <class D>
-hipError_t launch_batch_m(const ImgDev *d, int n, int64_t total, int mode, int waves, int grid,
+template <class D, int MODE>
+hipError_t launch_batch_w(const ImgDev *d, int n, int64_t total, int waves, int th, int grid,
                           hipStream_t s) {
-    return mode == MODE_DIRECT25 ? launch_batch_w<D, MODE_DIRECT25>(d, n, total, waves, grid, s)
-                                 : launch_batch_w<D, MODE_FUSED>(d, n, total, waves, grid, s);
+    switch (waves) {
+    case 1: return launch_batch_th<D, MODE, 1>(d, n, total, th, grid, s);
+    case 2: return launch_batch_th<D, MODE, 2>(d, n, total, th, grid, s);
+    default: return launch_batch_th<D, MODE, 4>(d, n, total, th, grid, s);
+    }
+}
+
+template <class D>
+hipError_t launch_batch_t(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
+                          int grid, hipStream_t s) {
+    return mode == MODE_DIRECT25 ? launch_batch_w<D, MODE_DIRECT25>(d, n, total, waves, th, grid, s)
+                                 : launch_batch_w<D, MODE_FUSED>(d, n, total, waves, th, grid, s);
 }
 
 }  // namespace
-
-hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
-                        hipStream_t s) {
-    switch (dtype) {
-    case 0: return launch_image_a<F32>(im, mode, waves, nblocks, s);
-    case 1: return launch_image_a<F16>(im, mode, waves, nblocks, s);
-    default: return launch_image_a<BF16>(im, mode, waves, nblocks, s);
-    }
-}
-
-hipError_t launch_batch(const ImgDev *d_descs, int n, int64_t total_tiles, int dtype, int mode,
-                        int waves, int grid, hipStream_t s) {
-    switch (dtype) {
-    case 0: return launch_batch_m<F32>(d_descs, n, total_tiles, mode, waves, grid, s);
-    case 1: return launch_batch_m<F16>(d_descs, n, total_tiles, mode, waves, grid, s);
-    default: return launch_batch_m<BF16>(d_descs, n, total_tiles, mode, waves, grid, s);
-    }
-}
 
 }  // namespace convsep5

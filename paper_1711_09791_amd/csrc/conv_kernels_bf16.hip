@@ -1,0 +1,16 @@
+// conv_kernels_bf16.hip -- instantiates the convolution kernels for BF16 storage.
+#include "conv_kernels.h"
+
+namespace convsep5 {
+
+hipError_t launch_image_bf16(const ImgDev &im, int mode, int waves, int64_t nblocks,
+                          hipStream_t s) {
+    return launch_image_t<BF16>(im, mode, waves, nblocks, s);
+}
+
+hipError_t launch_batch_bf16(const ImgDev *d_descs, int n, int64_t total_tiles, int mode,
+                          int waves, int th, int grid, hipStream_t s) {
+    return launch_batch_t<BF16>(d_descs, n, total_tiles, mode, waves, th, grid, s);
+}
+
+}  // namespace convsep5

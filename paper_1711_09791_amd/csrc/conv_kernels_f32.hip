@@ -1,0 +1,16 @@
+// conv_kernels_f32.hip -- instantiates the convolution kernels for F32 storage.
+#include "conv_kernels.h"
+
+namespace convsep5 {
+
+hipError_t launch_image_f32(const ImgDev &im, int mode, int waves, int64_t nblocks,
+                          hipStream_t s) {
+    return launch_image_t<F32>(im, mode, waves, nblocks, s);
+}
+
+hipError_t launch_batch_f32(const ImgDev *d_descs, int n, int64_t total_tiles, int mode,
+                          int waves, int th, int grid, hipStream_t s) {
+    return launch_batch_t<F32>(d_descs, n, total_tiles, mode, waves, th, grid, s);
+}
+
+}  // namespace convsep5

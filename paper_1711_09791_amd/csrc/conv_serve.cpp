@@ -48,6 +48,7 @@ struct Req {
     uint64_t footprint = 0;
     conv_req_times t{};
     int state = QUEUED;
+    hipEvent_t ready = nullptr;  // recorded on the producer stream at submit
 };
 
 struct Launch {
@@ -64,7 +65,8 @@ struct conv_server {
     int device = 0;
     std::vector<hipStream_t> streams;
     std::vector<char> stream_busy;
-    std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> event_pool;   // launch-completion events
+    std::vector<hipEvent_t> ready_pool;   // producer-stream events of requests
     std::mutex mu;
     std::condition_variable cv;       // new work or stop
     std::condition_variable idle_cv;  // queue and in-flight both empty
@@ -153,6 +155,13 @@ void conv_server::launch_locked() {
         int dt = 0;
         conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
                                      CONV_1PASS_FUSED, tc, &descs, &total, &dt);
+        // the launch starts only after each request's producer work
+        for (Req *r : L.reqs) {
+            if (st == CONV_OK && hipStreamWaitEvent(streams[s], r->ready, 0) != hipSuccess)
+                st = CONV_EHIP;
+            ready_pool.push_back(r->ready);
+            r->ready = nullptr;
+        }
         if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, streams[s]);
         if (event_pool.empty()) {
             hipEvent_t e = nullptr;
@@ -244,7 +253,7 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
 }
 
 conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, const float k[5],
-                              const conv_image *img, uint64_t *ticket) {
+                              const conv_image *img, hipStream_t stream, uint64_t *ticket) {
     clear_error();
     if (!srv || !ticket || !k) return set_error(CONV_EINVAL, "NULL argument");
     Layout L;
@@ -259,7 +268,28 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     if (fp > srv->cfg.hbm_budget_bytes)
         return set_error(CONV_ENOMEM, "footprint %llu exceeds the budget %llu",
                          (unsigned long long)fp, (unsigned long long)srv->cfg.hbm_budget_bytes);
+    hipEvent_t ready = nullptr;
+    if (!L.empty) {
+        {
+            std::lock_guard<std::mutex> g(srv->mu);
+            if (!srv->ready_pool.empty()) {
+                ready = srv->ready_pool.back();
+                srv->ready_pool.pop_back();
+            }
+        }
+        hipError_t e = hipSuccess;
+        if (!ready) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ready, stream);
+        if (e != hipSuccess) {
+            if (ready) {
+                std::lock_guard<std::mutex> g(srv->mu);
+                srv->ready_pool.push_back(ready);
+            }
+            return hip_error(e, "recording the request's ready event");
+        }
+    }
     auto *r = new Req();
+    r->ready = ready;
     r->in = d_in;
     r->out = d_out;
     for (int i = 0; i < 5; ++i) r->k[i] = k[i];
@@ -269,6 +299,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     {
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->stop) {
+            if (r->ready) srv->ready_pool.push_back(r->ready);
             delete r;
             return set_error(CONV_EINVAL, "server is shutting down");
         }
@@ -336,6 +367,7 @@ conv_status conv_serve_destroy(conv_server *srv) {
     hipGetDevice(&prev);
     hipSetDevice(srv->device);
     for (hipEvent_t e : srv->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : srv->ready_pool) hipEventDestroy(e);
     for (hipStream_t s : srv->streams) hipStreamDestroy(s);
     hipSetDevice(prev);
     for (auto &kv : srv->reqs) delete kv.second;

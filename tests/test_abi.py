@@ -176,3 +176,16 @@ def test_binding_describes_tensors():
     assert (i.planes, i.rows, i.cols, i.dtype, i.pitch, i.plane_stride) == (3, 10, 12, 2, 20, 240)
     with pytest.raises(TypeError):
         cs.image_of(torch.zeros(2, 2, 2, dtype=torch.float64))
+
+
+def test_binding_rejects_mismatched_output_layout():
+    import torch
+
+    a = torch.zeros(3, 10, 12)
+    with pytest.raises(ValueError):
+        cs.conv_sep5_1pass(a, torch.zeros(3, 10, 13), [1, 4, 6, 4, 1])
+    with pytest.raises(ValueError):
+        cs.conv_sep5_2pass(a, torch.zeros(3, 10, 12, dtype=torch.float16), [1, 4, 6, 4, 1])
+    big = torch.zeros(3, 10, 16)
+    with pytest.raises(ValueError):
+        cs.conv_sep5_batch([a], [big[:, :, :12]], [[1, 4, 6, 4, 1]])

@@ -76,12 +76,16 @@ def test_batch_mixed_layouts_and_empty_images():
         hosts.append(h)
         ins.append(torch.from_numpy(h).cuda())
         ks.append(synth.taps_random(400 + i))
-    # one image as an unaligned view
+    # one image as an unaligned view (its output is the same view of another buffer)
     big = torch.zeros(3, 130, 520, device="cuda")
     big[:, :, 1:518] = ins[4]
     ins[4] = big[:, :, 1:518]
     outs = [torch.full(a.shape, float("nan"), device="cuda") for a in ins]
+    big_out = torch.full((3, 130, 520), 777.0, device="cuda")
+    outs[4] = big_out[:, :, 1:518]
+    outs[4].fill_(float("nan"))
     cs.conv_sep5_batch(ins, outs, ks)
+    assert torch.all(big_out[:, :, 0] == 777.0) and torch.all(big_out[:, :, 518:] == 777.0)
     for i, s in enumerate(shapes):
         if 0 in s:
             continue
