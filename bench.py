@@ -1,15 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the width-5 separable convolution on one MI355X.
 
-Workload: one 3-plane 4096 x 4096 FP32 image (uniform [0,1) pixels, seed 1),
-positive random taps normalised to sum 1 (seed 2); 2-pixel border = 0.
+Headline workload: one 3-plane 4096 x 4096 FP32 image (uniform [0,1) pixels,
+seed 1), positive random taps normalised to sum 1 (seed 2); 2-pixel border 0.
 A step is one fused single-pass convolution of the image (input read, row
-filter, on-chip intermediate, column filter, border, output store).  The
-two-pass form (HBM intermediate) and the direct 25-tap form are timed the same
-way and reported under "forms"; a device copy of the same bytes is the
-achievable ceiling.  Inputs are resident in HBM; the timed launches rotate over
-several input/output buffer sets so the working set exceeds the 256 MB
-Infinity Cache.
+filter, on-chip intermediate, column filter, border, output store); `value` is
+its MPix/s.  Inputs are resident in HBM; timed launches rotate over several
+input/output buffer sets so the working set exceeds the 256 MB Infinity Cache.
+
+Also measured and reported in the same JSON line:
+  forms      the two-pass form (HBM intermediate), the direct 25-tap form and a
+             device copy of the same bytes (the achievable ceiling);
+  precision  the fused form with FP16 and BF16 storage (FP32 accumulation);
+  batch      64 uneven images (H, W = 8*U{30..270}) in one persistent launch,
+             eager and as a captured graph, against one launch per image;
+  serving    Poisson arrivals of 640x480 .. 3840x2160 frames, each with its
+             own taps: p50/p99 latency of the continuous-batching server
+             against the same server restricted to one image per launch, at
+             0.5x and 0.8x of the batched server's measured capacity;
+  cpu_baseline  the FP64 oracle on the host cores, on the whole image.
 
 Prints ONE JSON line.  Run with no flags for the default configuration.
 """
@@ -41,6 +50,12 @@ def parse():
     ap.add_argument("--sets", type=int, default=3, help="rotating buffer sets")
     ap.add_argument("--forms", default="fused,2pass,direct25,copy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision, batch and serving measurements")
+    ap.add_argument("--warm", action="store_true",
+                    help="also time the fused form on one buffer set (cache-warm)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--cpu-min-s", type=float, default=10.0,
                     help="repeat the oracle until this much CPU time is spent")
     return ap.parse_args()
@@ -70,6 +85,240 @@ def traffic_for(form: str):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def timed(torch, fn, steps, warmup):
+    """Total ms over `steps` calls and sorted per-call ms, from HIP events on
+    torch's current stream (the stream every call here launches on)."""
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for i in range(steps):
+        ev[i][0].record()
+        fn(i)
+        ev[i][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    return total, per
+
+
+def check(cs, st):
+    if st != 0:
+        raise cs.ConvError(st, cs.conv_last_error())
+
+
+def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "direct25", "copy")):
+    """One 3x4096x4096 image, rotating buffer sets; returns per-form figures."""
+    dev = torch.device("cuda:0")
+    base = torch.from_numpy(host).to(dev)
+    if dtype is not None:
+        base = base.to(dtype)
+    esz = base.element_size()
+    S = max(1, args.sets)
+    ins = [base] + [base.clone() for _ in range(S - 1)]
+    outs = [torch.empty_like(base) for _ in range(S)]
+    tmp = torch.empty(P * R * C, device=dev) if "2pass" in forms else None
+    L = cs.lib()
+    img = cs.image_of(base)
+    kk = (ctypes.c_float * 5)(*[float(v) for v in k])
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+    pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
+    ptmp = ctypes.c_void_p(tmp.data_ptr()) if tmp is not None else None
+    pimg = ctypes.byref(img)
+    steps_fn = {
+        "fused": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 0, hs)),
+        "direct25": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 1, hs)),
+        "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, pimg, hs)),
+        "copy": lambda i: outs[i % S].copy_(ins[i % S]),
+    }
+    alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz}
+    res = {}
+    for name in forms:
+        total, per = timed(torch, steps_fn[name], args.steps, args.warmup)
+        avg = sum(per) / len(per)
+        nbytes = alg_bytes[name] * P * R * C
+        res[name] = {
+            "ms_per_step": total / args.steps,
+            "avg_launch_ms": avg,
+            "median_launch_ms": per[len(per) // 2],
+            "mpix_per_s": (R * C) / (total / args.steps * 1e-3) / 1e6,
+            "alg_bytes_per_step": nbytes,
+            "alg_GBps": nbytes / (avg * 1e-3) / 1e9,
+            "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
+    if "fused" in res and getattr(args, "warm", False):
+        fn = lambda i: check(cs, L.conv_sep5_1pass(pin[0], pout[0], kk, pimg, 0, hs))  # noqa: E731
+        _, per = timed(torch, fn, args.steps, args.warmup)
+        res["fused"]["warm_same_buffers_avg_launch_ms"] = sum(per) / len(per)
+    if "fused" in res and "copy" in res:
+        res["fused"]["frac_of_copy"] = res["copy"]["avg_launch_ms"] / res["fused"]["avg_launch_ms"]
+    eq = None
+    if "fused" in res and "2pass" in res:
+        o1, o2 = torch.empty_like(base), torch.empty_like(base)
+        cs.conv_sep5_1pass(base, o1, k)
+        cs.conv_sep5_2pass(base, o2, k, d_tmp=tmp)
+        torch.cuda.synchronize()
+        eq = bool(torch.equal(o1, o2))
+    del ins, outs, tmp
+    return res, eq
+
+
+def bench_batch(torch, cs, synth, args):
+    """64 uneven FP32 images: persistent batch launch, graph replay, per-image launches."""
+    shapes = synth.batch_shapes(3, 64)
+    ins = [torch.from_numpy(synth.image(100 + i, 3, h, w)).cuda() for i, (h, w) in enumerate(shapes)]
+    outs = [torch.empty_like(a) for a in ins]
+    ks = [synth.taps_random(200 + i) for i in range(64)]
+    pix = sum(h * w for h, w in shapes)
+    nbytes = 24 * pix
+    steps = max(10, args.steps // 10)
+    t_eager, _ = timed(torch, lambda i: cs.conv_sep5_batch(ins, outs, ks), steps, 3)
+    plan = cs.conv_batch_plan_create(ins, outs, ks)
+    t_graph, _ = timed(torch, lambda i: plan.launch(), steps, 3)
+    plan.destroy()
+    t_lone, _ = timed(torch, lambda i: [cs.conv_sep5_1pass(a, o, k) for a, o, k in zip(ins, outs, ks)],
+                      steps, 3)
+    cfg = cs.conv_get_tile_cfg(0, 1).as_dict()
+    ms_e, ms_g, ms_l = t_eager / steps, t_graph / steps, t_lone / steps
+    return {
+        "images": 64, "mpix": pix / 1e6, "alg_bytes": nbytes, "tile_cfg": cfg,
+        "eager_ms": ms_e, "graph_ms": ms_g, "per_image_launches_ms": ms_l,
+        "eager_mpix_per_s": pix / (ms_e * 1e-3) / 1e6,
+        "graph_mpix_per_s": pix / (ms_g * 1e-3) / 1e6,
+        "per_image_mpix_per_s": pix / (ms_l * 1e-3) / 1e6,
+        "graph_alg_GBps": nbytes / (ms_g * 1e-3) / 1e9,
+        "graph_frac_of_hbm_peak": nbytes / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "speedup_vs_per_image": ms_l / ms_g,
+    }
+
+
+def bench_serving(torch, cs, synth, args, sizes=None):
+    """Poisson request stream (arrival times kept by the native load generator);
+    continuous batching vs one conv_sep5_1pass launch per request."""
+    G = cs.loadgen_lib()
+    sizes = list(sizes or synth.SERVE_SIZES)
+    NBUF = 64  # >= max_slots: two requests admitted together never share a buffer
+    bufs = {}
+    for (h, w) in sizes:
+        ins = [torch.rand(3, h, w, device="cuda") for _ in range(NBUF)]
+        outs = [torch.empty_like(ins[0]) for _ in range(NBUF)]
+        bufs[(h, w)] = (ins, outs, cs.image_of(ins[0]))
+    torch.cuda.synchronize()
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    budget = 8 << 30
+
+    def requests(n, rate, seed):
+        arrivals, req_sizes = synth.serving_stream(seed, seed + 1, n, rate if rate else 1.0, sizes)
+        if not rate:
+            arrivals = arrivals * 0.0  # everything at once: capacity probe
+        arr = (ctypes.c_double * n)(*[float(a) for a in arrivals])
+        pin, pout = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+        imgs = (cs.conv_image * n)()
+        flat = []
+        counters = {s: 0 for s in sizes}
+        for i, s in enumerate(req_sizes):
+            ins, outs, img = bufs[s]
+            j = counters[s] % NBUF
+            counters[s] += 1
+            pin[i], pout[i], imgs[i] = ins[j].data_ptr(), outs[j].data_ptr(), img
+            flat.extend(float(v) for v in synth.taps_random(6000 + i))
+        kk = (ctypes.c_float * (5 * n))(*flat)
+        return arr, pin, pout, kk, imgs
+
+    q = lambda v, p: v[min(len(v) - 1, int(p * len(v)))]  # noqa: E731
+
+    def summarize(sub, done, lag, n, warm, rate, extra):
+        lat = sorted((d - s) / 1e3 for s, d in zip(sub[warm:], done[warm:]))
+        span = (max(done[warm:]) - min(sub[warm:])) / 1e9
+        lg = sorted(lag)
+        return {"p50_us": q(lat, 0.50), "p99_us": q(lat, 0.99), "mean_us": sum(lat) / len(lat),
+                "throughput_req_per_s": (n - warm) / span, "offered_req_per_s": rate,
+                "submit_lag_p99_us": q(lg, 0.99) * 1e6, **extra}
+
+    def run_server(max_batch, n_streams, max_bytes, rate, n, warm, seed=5):
+        arr, pin, pout, kk, imgs = requests(n, rate, seed)
+        # inputs are static and synchronised: no producer ordering, like the
+        # direct-launch baseline
+        srv = cs.Server(budget, max_slots=NBUF, n_streams=n_streams, max_batch=max_batch,
+                        max_batch_bytes=max_bytes, producer_wait=False)
+        tickets = (ctypes.c_uint64 * n)()
+        lag = (ctypes.c_double * n)()
+        check(cs, G.conv_loadgen_serve(srv._h, n, arr, pin, pout, kk, imgs, hs, tickets, lag))
+        srv.drain()
+        times = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+        srv.destroy()
+        w = times[warm:]
+        mean = lambda a, b: sum(t[b] - t[a] for t in w) / len(w) / 1e3  # noqa: E731
+        stages = {"queue_us": mean("submit_ns", "admit_ns"), "enqueue_us": mean("admit_ns", "launch_ns"),
+                  "device_us": mean("launch_ns", "done_ns"),
+                  "mean_batch": sum(t["batch_size"] for t in w) / len(w)}
+        return summarize([t["submit_ns"] for t in times], [t["done_ns"] for t in times], list(lag),
+                         n, warm, rate, {"launches": st["launches"], "max_batch_seen": st["max_batch"],
+                                         "max_streams_busy": st["max_streams_busy"],
+                                         "mean_stages": stages})
+
+    def run_direct(n_streams, rate, n, warm, seed=5):
+        arr, pin, pout, kk, imgs = requests(n, rate, seed)
+        sub, done = (ctypes.c_uint64 * n)(), (ctypes.c_uint64 * n)()
+        lag = (ctypes.c_double * n)()
+        check(cs, G.conv_loadgen_direct(n, arr, pin, pout, kk, imgs, n_streams, sub, done, lag))
+        return summarize(list(sub), list(done), list(lag), n, warm, rate, {"launches": n})
+
+    MB = 1 << 20
+    policies = {
+        "batched": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm),
+        "batched_8_streams": lambda rate, n, warm: run_server(16, 8, 128 * MB, rate, n, warm),
+        "batched_count_cap_only": lambda rate, n, warm: run_server(16, 4, 0, rate, n, warm),
+        "per_image_launch": lambda rate, n, warm: run_direct(1, rate, n, warm),
+        "per_image_launch_4_streams": lambda rate, n, warm: run_direct(4, rate, n, warm),
+    }
+    caps = {name: fn(0.0, 2000, 0)["throughput_req_per_s"] for name, fn in policies.items()}
+    capacity = caps["batched"]
+    out = {"capacity_req_per_s": caps,
+           "batched_policy": {"max_batch": 16, "streams": 4, "max_slots": NBUF,
+                              "max_batch_bytes": 128 * MB, "hbm_budget_bytes": budget},
+           "sizes": [f"3x{h}x{w}" for (h, w) in sizes], "levels": {}}
+    n = args.serve_requests + args.serve_warmup
+    for frac in (0.5, 0.8):
+        lam = frac * capacity
+        lvl = {"rate_req_per_s": lam}
+        for name, fn in policies.items():
+            lvl[name] = fn(lam, n, args.serve_warmup)
+        out["levels"][f"{frac:.1f}x_batched_capacity"] = lvl
+    return out
+
+
+def cpu_baseline(oracle, np, host, k, args):
+    A64 = host.astype(np.float64)
+    k64 = k.astype(np.float64)
+    times = []
+    t_start = time.perf_counter()
+    while (len(times) < 3 or time.perf_counter() - t_start < args.cpu_min_s) and len(times) < 200:
+        t = time.perf_counter()
+        oracle.conv5(A64, k64, nthreads=0)
+        times.append(time.perf_counter() - t)
+        if time.perf_counter() - t_start > 3 * args.cpu_min_s:
+            break
+    times.sort()
+    med = times[len(times) // 2]
+    return {
+        "value": (R * C) / med / 1e6,
+        "unit": "MPix/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"whole 3x{R}x{C} image, FP64 direct 25-term oracle (OpenMP over plane x "
+                  f"row), median of {len(times)} run(s), {med:.3f} s each",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -84,140 +333,49 @@ def main():
     import paper_1711_09791_amd as cs
     from paper_1711_09791_amd import synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
     host = synth.image(1, P, R, C)
     k = synth.taps_random(2)
-    base = torch.from_numpy(host).to(dev)
-    S = max(1, args.sets)
-    ins = [base] + [base.clone() for _ in range(S - 1)]
-    outs = [torch.empty_like(base) for _ in range(S)]
-    tmp = torch.empty(P * R * C, device=dev)
-    stream = torch.cuda.current_stream()
+    forms_list = [f for f in args.forms.split(",") if f]
+    forms, eq = bench_image(torch, cs, host, k, args, forms=forms_list)
 
-    # Prepared C-ABI arguments: the timed loop makes one foreign call per step.
-    L = cs.lib()
-    img = cs.image_of(base)
-    kk = (ctypes.c_float * 5)(*[float(v) for v in k])
-    hs = ctypes.c_void_p(stream.cuda_stream)
-    pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
-    pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
-    ptmp = ctypes.c_void_p(tmp.data_ptr())
-    pimg = ctypes.byref(img)
-
-    def call(st):
-        if st != 0:
-            raise cs.ConvError(st, cs.conv_last_error())
-
-    steps_fn = {
-        "fused": lambda i: call(L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 0, hs)),
-        "direct25": lambda i: call(L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 1, hs)),
-        "2pass": lambda i: call(L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, pimg, hs)),
-        "copy": lambda i: outs[i % S].copy_(ins[i % S]),
-    }
-    alg_bytes = {  # algorithmic HBM bytes per step
-        "fused": 8 * P * R * C, "direct25": 8 * P * R * C, "2pass": 16 * P * R * C,
-        "copy": 8 * P * R * C,
-    }
-
-    def timed(fn, steps, warmup):
-        for i in range(warmup):
-            fn(i)
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record()
-        for i in range(steps):
-            ev[i][0].record()
-            fn(i)
-            ev[i][1].record()
-        t1.record()
-        torch.cuda.synchronize()
-        total = t0.elapsed_time(t1)
-        per = sorted(a.elapsed_time(b) for a, b in ev)
-        return total, per
-
-    forms = {}
-    for name in [f for f in args.forms.split(",") if f]:
-        total, per = timed(steps_fn[name], args.steps, args.warmup)
-        avg = sum(per) / len(per)
-        forms[name] = {
-            "ms_per_step": total / args.steps,
-            "avg_launch_ms": avg,
-            "median_launch_ms": per[len(per) // 2],
-            "mpix_per_s": (R * C) / (total / args.steps * 1e-3) / 1e6,
-            "alg_GBps": alg_bytes[name] / (avg * 1e-3) / 1e9,
-            "frac_of_hbm_peak": alg_bytes[name] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        }
-    # warm number for the fused form: the same buffer set every step
-    if "fused" in forms:
-        fn = lambda i: call(L.conv_sep5_1pass(pin[0], pout[0], kk, pimg, 0, hs))  # noqa: E731
-        total, per = timed(fn, args.steps, args.warmup)
-        forms["fused"]["warm_same_buffers_avg_launch_ms"] = sum(per) / len(per)
-    if "copy" in forms and "fused" in forms:
-        forms["fused"]["frac_of_copy"] = forms["copy"]["avg_launch_ms"] / forms["fused"]["avg_launch_ms"]
-
-    # consistency of the timed outputs: fused and two-pass are bitwise equal
-    check = None
-    if "fused" in forms and "2pass" in forms:
-        o1, o2 = torch.empty_like(base), torch.empty_like(base)
-        cs.conv_sep5_1pass(base, o1, k)
-        cs.conv_sep5_2pass(base, o2, k, d_tmp=tmp)
-        torch.cuda.synchronize()
-        check = bool(torch.equal(o1, o2))
+    extras = {}
+    if not args.no_extras:
+        prec = {}
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            r, _ = bench_image(torch, cs, host, k, args, dtype=dt, forms=("fused", "direct25"))
+            prec[name] = r
+        extras["precision"] = prec
+        extras["batch"] = bench_batch(torch, cs, synth, args)
+        extras["serving"] = bench_serving(torch, cs, synth, args)
+        extras["serving_small_frames"] = bench_serving(torch, cs, synth, args, sizes=[(480, 640)])
 
     main_form = "fused"
     f = forms[main_form]
-    traffic = traffic_for(main_form)
     roofline = {
         "bound": "hbm",
         "achieved": f["alg_GBps"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": f["alg_GBps"] / HBM_PEAK_GBS,
-        "traffic": traffic,
-        "kernel": "fused single-pass FP32 (k_image<F32,aligned,FUSED>)",
-        "alg_bytes_per_launch": alg_bytes[main_form],
+        "traffic": traffic_for(main_form),
+        "kernel": "k_image<F32, aligned, FUSED, 2 waves, 8-row bands>",
+        "alg_bytes_per_launch": f["alg_bytes_per_step"],
     }
-
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        A64 = host.astype(np.float64)
-        k64 = k.astype(np.float64)
-        times = []
-        t_start = time.perf_counter()
-        while (len(times) < 3 or time.perf_counter() - t_start < args.cpu_min_s) \
-                and len(times) < 200:
-            t = time.perf_counter()
-            oracle.conv5(A64, k64, nthreads=0)
-            times.append(time.perf_counter() - t)
-            if time.perf_counter() - t_start > 3 * args.cpu_min_s:
-                break
-        times.sort()
-        med = times[len(times) // 2]
-        cpu = {
-            "value": (R * C) / med / 1e6,
-            "unit": "MPix/s",
-            "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"whole 3x{R}x{C} image, FP64 direct 25-term oracle (OpenMP over "
-                      f"plane x row), median of {len(times)} run(s), {med:.3f} s each",
-        }
+        cpu = cpu_baseline(oracle, np, host, k, args)
 
-    ms = forms[main_form]["ms_per_step"]
     line = {
         "metric": "MPix/s (3-plane) + % HBM roofline; serving p50/p99 latency vs per-image launch",
-        "value": forms[main_form]["mpix_per_s"],
+        "value": f["mpix_per_s"],
         "unit": "MPix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": f["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -229,12 +387,14 @@ def main():
             "planes": P, "rows": R, "cols": C,
             "taps": "positive random, normalised to sum 1 (seed 2)",
             "pixels": "uniform [0,1) (seed 1)",
-            "buffer_sets_rotated": S,
+            "buffer_sets_rotated": max(1, args.sets),
+            "tile_cfg": cs.conv_get_tile_cfg(0, 0).as_dict(),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
-        "fused_equals_2pass_bitwise": check,
+        "fused_equals_2pass_bitwise": eq,
+        **extras,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -164,11 +164,16 @@ conv_status conv_batch_plan_destroy(conv_plan *plan);
  *                  (1, 2 or 4)
  *   persist_wgs_per_cu  batch kernel: resident workgroups per compute unit
  *                  (1..32); the persistent grid is this times the CU count
+ *   xcd_slabs      0: workgroups take tiles in launch order, so the resident
+ *                  waves sweep the image (or batch) as one compact window;
+ *                  1: each of the 8 XCDs takes one contiguous slab of tiles
+ *                  (full rows), so horizontal halos stay in that XCD's L2
  */
 typedef struct {
     int32_t rows_per_tile;
     int32_t waves_per_wg;
     int32_t persist_wgs_per_cu;
+    int32_t xcd_slabs;
 } conv_tile_cfg;
 
 /* kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel. */
@@ -202,6 +207,13 @@ typedef struct {
     int32_t n_streams;         /* launch streams (1..16)                     */
     int32_t max_batch;         /* max requests per launch (>= 1)             */
     int32_t device;            /* HIP device ordinal (-1: current device)    */
+    uint64_t max_batch_bytes;  /* max footprint per launch (0: no limit); a
+                                  request larger than this runs alone      */
+    int32_t producer_wait;     /* 1: order each launch after the submitters'
+                                  streams (an event per submit, see
+                                  conv_serve_submit); 0: the caller promises
+                                  every input is complete when it submits  */
+    int32_t reserved;
 } conv_serve_cfg;
 
 typedef struct {
@@ -218,9 +230,10 @@ typedef struct conv_server conv_server;
 conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv);
 /* Non-blocking.  d_in/d_out: device image (FP32/FP16/BF16) as in
  * conv_sep5_1pass; k: 5 host taps.  `stream` is the caller's producer stream
- * (NULL: the default stream): work enqueued on it before this call -- the
- * writes that fill d_in, say -- completes before the request's kernel starts
- * (an event is recorded on it here and waited on by the launch).  Footprint
+ * (NULL: the default stream): with producer_wait = 1, work enqueued on it
+ * before this call -- the writes that fill d_in, say -- completes before the
+ * request's kernel starts (an event is recorded on it here and waited on by
+ * the launch); with producer_wait = 0 it is ignored.  Footprint
  * larger than the budget -> CONV_ENOMEM; bad arguments -> CONV_EINVAL /
  * CONV_EALIAS.  *ticket > 0. */
 conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out,

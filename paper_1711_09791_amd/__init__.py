@@ -18,6 +18,7 @@ from typing import Iterable, Sequence
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libconvsep5.so")
+LOADGEN_PATH = os.path.join(_PKG, "libconvsep5_loadgen.so")
 
 CONV_OK, CONV_EINVAL, CONV_EALIAS, CONV_ENOMEM = 0, -1, -2, -3
 CONV_EHIP, CONV_EAGAIN, CONV_ENOTFOUND = -4, -5, -6
@@ -37,7 +38,7 @@ class conv_image(ctypes.Structure):
 
 class conv_tile_cfg(ctypes.Structure):
     _fields_ = [("rows_per_tile", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
-                ("persist_wgs_per_cu", ctypes.c_int32)]
+                ("persist_wgs_per_cu", ctypes.c_int32), ("xcd_slabs", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -46,7 +47,8 @@ class conv_tile_cfg(ctypes.Structure):
 class conv_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64),
+                ("producer_wait", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class conv_req_times(ctypes.Structure):
@@ -129,6 +131,35 @@ def lib():
     L.conv_version.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+_loadgen = None
+
+LOADGEN_EXPORTS = ("conv_loadgen_serve", "conv_loadgen_direct")
+
+
+def loadgen_lib():
+    """libconvsep5_loadgen.so (open-loop request generator for benchmarks)."""
+    global _loadgen
+    if _loadgen is not None:
+        return _loadgen
+    lib()
+    if not os.path.exists(LOADGEN_PATH):
+        raise RuntimeError(f"{LOADGEN_PATH} is not built")
+    G = ctypes.CDLL(LOADGEN_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    dp = ctypes.POINTER(ctypes.c_double)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    G.conv_loadgen_serve.argtypes = [vp, i32, dp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(ctypes.c_float), ctypes.POINTER(conv_image),
+                                     vp, u64p, dp]
+    G.conv_loadgen_serve.restype = ctypes.c_int
+    G.conv_loadgen_direct.argtypes = [i32, dp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(ctypes.c_float), ctypes.POINTER(conv_image),
+                                      i32, u64p, u64p, dp]
+    G.conv_loadgen_direct.restype = ctypes.c_int
+    _loadgen = G
+    return G
 
 
 def conv_last_error() -> str:
@@ -294,8 +325,9 @@ def conv_get_tile_cfg(dtype: int, kind: int) -> conv_tile_cfg:
 
 
 def conv_set_tile_cfg(dtype: int, kind: int, rows_per_tile: int, waves_per_wg: int,
-                      persist_wgs_per_cu: int = 0):
-    c = conv_tile_cfg(int(rows_per_tile), int(waves_per_wg), int(persist_wgs_per_cu))
+                      persist_wgs_per_cu: int = 0, xcd_slabs: int = 0):
+    c = conv_tile_cfg(int(rows_per_tile), int(waves_per_wg), int(persist_wgs_per_cu),
+                      int(xcd_slabs))
     return _check(lib().conv_set_tile_cfg(int(dtype), int(kind), ctypes.byref(c)))
 
 
@@ -313,9 +345,11 @@ class Server:
     """Continuous-batching server (see conv_serve_* in the C header)."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
-                 max_batch: int = 64, device: int = -1):
+                 max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
+                 producer_wait: bool = True):
         cfg = conv_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(n_streams),
-                             int(max_batch), int(device))
+                             int(max_batch), int(device), int(max_batch_bytes),
+                             int(bool(producer_wait)), 0)
         h = ctypes.c_void_p()
         _check(lib().conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -361,8 +395,10 @@ class Server:
 
 
 def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
-                      max_batch: int = 64, device: int = -1) -> Server:
-    return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device)
+                      max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
+                      producer_wait: bool = True) -> Server:
+    return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device, max_batch_bytes,
+                  producer_wait)
 
 
 def conv_serve_submit(srv: Server, d_in, d_out, k, img=None, stream=None) -> int:

@@ -19,6 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libconvsep5.so")
+LOADGEN_LIB = os.path.join(PKG, "libconvsep5_loadgen.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["conv_kernels_f32.hip", "conv_kernels_f16.hip", "conv_kernels_bf16.hip",
@@ -61,8 +62,17 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the serving load generator: a separate library on top of the public ABI
+    obj = _compile("conv_loadgen.cpp")
+    tmp = LOADGEN_LIB + ".tmp%d" % os.getpid()
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", tmp,
+           f"-L{PKG}", "-lconvsep5", "-Wl,-rpath,$ORIGIN", "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed (loadgen):\n{r.stderr}")
+    os.replace(tmp, LOADGEN_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", LOADGEN_LIB)
     return LIB
 
 

@@ -87,9 +87,9 @@ static std::mutex g_cfg_mu;
 // Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image; the
 // 64-image uneven batch); conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][2] = {
-    {{8, 2, 0}, {16, 1, 8}},
-    {{32, 4, 0}, {16, 1, 8}},
-    {{32, 4, 0}, {16, 1, 8}},
+    {{8, 2, 0, 0}, {16, 1, 8, 0}},
+    {{32, 4, 0, 0}, {16, 1, 8, 0}},
+    {{32, 4, 0, 0}, {16, 1, 8, 0}},
 };
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
@@ -101,6 +101,7 @@ static bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
     if (kind == 1 && (c->persist_wgs_per_cu < 1 || c->persist_wgs_per_cu > 32)) return false;
+    if (c->xcd_slabs != 0 && c->xcd_slabs != 1) return false;
     return true;
 }
 
@@ -131,6 +132,7 @@ int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_i
     d->nsg = (d->ns + cfg.waves_per_wg - 1) / cfg.waves_per_wg;
     d->th = cfg.rows_per_tile;
     d->nb = (img->rows + d->th - 1) / d->th;
+    d->xcd_slabs = cfg.xcd_slabs;
     fill_taps(&d->tp, k);
     if (L.empty) return 0;
     return (int64_t)img->planes * d->nsg * d->nb;
@@ -295,6 +297,19 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
     DeviceState *st = nullptr;
     conv_status rc = device_state(&st);
     if (rc != CONV_OK) return rc;
+    if ((int)descs.size() <= kMaxArgImages) {
+        // small batch: descriptors ride in the kernel argument
+        BatchArgs a;
+        std::memset(&a, 0, sizeof a);
+        std::memcpy(a.d, descs.data(), descs.size() * sizeof(ImgDev));
+        a.n = (int)descs.size();
+        a.total = total;
+        const int64_t cap = (int64_t)st->cus * cfg.persist_wgs_per_cu;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+        hipError_t e = launch_batch_args(a, dtype, mode, cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
+        if (e != hipSuccess) return hip_error(e, "batch kernel launch");
+        return CONV_OK;
+    }
     DescSlot *slot = nullptr;
     rc = stage_descs(st, descs.data(), descs.size() * sizeof(ImgDev), s, &slot);
     if (rc != CONV_OK) return rc;

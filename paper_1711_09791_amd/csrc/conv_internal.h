@@ -36,9 +36,21 @@ struct ImgDev {
     int32_t nsg;          // strip groups (waves_per_wg strips each)
     int32_t nb;           // row bands
     int32_t th;           // output rows per band
+    int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles
+    int32_t reserved;
     int64_t tile_begin;   // batch: this image's first tile in the launch
     int64_t tile_end;     // batch: one past its last tile
     Taps tp;
+};
+
+// Batches of up to kMaxArgImages images travel as one kernel argument (no
+// descriptor copy before the launch); larger ones use a device table.
+constexpr int kMaxArgImages = 16;
+struct BatchArgs {
+    ImgDev d[kMaxArgImages];
+    int32_t n;
+    int32_t reserved;
+    int64_t total;
 };
 
 // Elements per lane per row: 16 bytes of storage.
@@ -57,6 +69,12 @@ hipError_t launch_batch_f16(const ImgDev *d, int n, int64_t total, int mode, int
                             int grid, hipStream_t s);
 hipError_t launch_batch_bf16(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
                              int grid, hipStream_t s);
+hipError_t launch_batch_args_f32(const BatchArgs &a, int mode, int waves, int th, int grid,
+                                 hipStream_t s);
+hipError_t launch_batch_args_f16(const BatchArgs &a, int mode, int waves, int th, int grid,
+                                 hipStream_t s);
+hipError_t launch_batch_args_bf16(const BatchArgs &a, int mode, int waves, int th, int grid,
+                                  hipStream_t s);
 
 inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
                                hipStream_t s) {
@@ -70,6 +88,13 @@ inline hipError_t launch_batch(const ImgDev *d, int n, int64_t total, int dtype,
     return dtype == 0 ? launch_batch_f32(d, n, total, mode, waves, th, grid, s)
          : dtype == 1 ? launch_batch_f16(d, n, total, mode, waves, th, grid, s)
                       : launch_batch_bf16(d, n, total, mode, waves, th, grid, s);
+}
+
+inline hipError_t launch_batch_args(const BatchArgs &a, int dtype, int mode, int waves, int th,
+                                    int grid, hipStream_t s) {
+    return dtype == 0 ? launch_batch_args_f32(a, mode, waves, th, grid, s)
+         : dtype == 1 ? launch_batch_args_f16(a, mode, waves, th, grid, s)
+                      : launch_batch_args_bf16(a, mode, waves, th, grid, s);
 }
 
 }  // namespace convsep5

@@ -582,28 +582,56 @@ __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave,
         run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
 }
 
-// One workgroup per logical tile, in launch order (so the resident waves
-// sweep the image row-band by row-band); grids above 2^20 workgroups loop.
+// Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8).
+// This renumbering gives each XCD one contiguous run of logical blocks.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n % X;
+    const int xcd = b % X, i = b / X;
+    return xcd * q + min(xcd, r) + i;
+}
+
+// One workgroup per logical tile; grids above 2^20 workgroups loop.  In
+// launch order (xcd_slabs = 0) the resident waves sweep the image row-band by
+// row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows.
 template <class D, bool AL, int MODE, int WAVES, int TH>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (int64_t lt = blockIdx.x; lt < nblocks; lt += gridDim.x)
-        run_tile<D, AL, MODE, WAVES, TH>(im, lt, wave, lane);
+    for (int64_t base = 0; base < nblocks; base += gridDim.x) {
+        const int64_t left = nblocks - base;
+        const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
+        if ((int)blockIdx.x >= cnt) break;
+        const int b = im.xcd_slabs ? xcd_remap(blockIdx.x, cnt) : (int)blockIdx.x;
+        run_tile<D, AL, MODE, WAVES, TH>(im, base + b, wave, lane);
+    }
 }
 
-// Persistent batch kernel: a fixed grid (a multiple of the CU count) strides
-// over the launch's tiles (images in order, then plane, band, strip group),
-// so the resident workgroups always work on one compact window of the batch.
+// Persistent batch kernel: a fixed grid (a multiple of the CU count) covers
+// the launch's tiles (images in order, then plane, band, strip group).  With
+// xcd_slabs = 0 the workgroups stride over the tiles, so the resident ones
+// always work on one compact window of the batch; with xcd_slabs = 1 each
+// workgroup takes one contiguous run, and the runs of one XCD are adjacent.
 // The owning image of each tile is found by advancing through the descriptor
 // table's tile ranges (tiles only increase within a workgroup).
 template <class D, int MODE, int WAVES, int TH>
-__global__ __launch_bounds__(WAVE *WAVES) void k_batch(const ImgDev *__restrict__ descs, int n,
-                                                       int64_t total) {
+__device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int n, int64_t total) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int G = gridDim.x;
+    int64_t t, end, step;
+    if (descs[0].xcd_slabs) {
+        const int64_t L = xcd_remap(blockIdx.x, G);
+        t = total * L / G;
+        end = total * (L + 1) / G;
+        step = 1;
+    } else {
+        t = blockIdx.x;
+        end = total;
+        step = G;
+    }
     int i = 0;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    for (; t < end; t += step) {
         while (i < n - 1 && t >= descs[i].tile_end) ++i;
         const ImgDev &im = descs[i];
         if (im.aligned)
@@ -611,6 +639,23 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_batch(const ImgDev *__restrict_
         else
             run_tile<D, false, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);
     }
+}
+
+template <class D, int MODE, int WAVES, int TH>
+__global__ __launch_bounds__(WAVE *WAVES) void k_batch(const ImgDev *__restrict__ descs, int n,
+                                                       int64_t total) {
+    batch_body<D, MODE, WAVES, TH>(descs, n, total);
+}
+
+// Same kernel with the descriptors in the kernel argument.  The argument is
+// read in place through the kernarg segment pointer (it is the only explicit
+// argument, so it starts at offset 0): indexing the by-value parameter itself
+// would make the compiler copy it to per-lane scratch memory.
+template <class D, int MODE, int WAVES, int TH>
+__global__ __launch_bounds__(WAVE *WAVES) void k_batch_args(BatchArgs) {
+    typedef const __attribute__((address_space(4))) BatchArgs ConstArgs;
+    ConstArgs *a = (ConstArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    batch_body<D, MODE, WAVES, TH>((const ImgDev *)a->d, a->n, a->total);
 }
 
 // ---- launchers -------------------------------------------------------------------
@@ -677,6 +722,33 @@ hipError_t launch_batch_t(const ImgDev *d, int n, int64_t total, int mode, int w
                           int grid, hipStream_t s) {
     return mode == MODE_DIRECT25 ? launch_batch_w<D, MODE_DIRECT25>(d, n, total, waves, th, grid, s)
                                  : launch_batch_w<D, MODE_FUSED>(d, n, total, waves, th, grid, s);
+}
+
+template <class D, int MODE, int WAVES>
+hipError_t launch_batch_args_th(const BatchArgs &a, int th, int grid, hipStream_t s) {
+    const dim3 blk(WAVE * WAVES);
+    switch (th) {
+    case 4: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 4>), dim3(grid), blk, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 8>), dim3(grid), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 0>), dim3(grid), blk, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <class D, int MODE>
+hipError_t launch_batch_args_w(const BatchArgs &a, int waves, int th, int grid, hipStream_t s) {
+    switch (waves) {
+    case 1: return launch_batch_args_th<D, MODE, 1>(a, th, grid, s);
+    case 2: return launch_batch_args_th<D, MODE, 2>(a, th, grid, s);
+    default: return launch_batch_args_th<D, MODE, 4>(a, th, grid, s);
+    }
+}
+
+template <class D>
+hipError_t launch_batch_args_t(const BatchArgs &a, int mode, int waves, int th, int grid,
+                               hipStream_t s) {
+    return mode == MODE_DIRECT25 ? launch_batch_args_w<D, MODE_DIRECT25>(a, waves, th, grid, s)
+                                 : launch_batch_args_w<D, MODE_FUSED>(a, waves, th, grid, s);
 }
 
 }  // namespace

@@ -13,4 +13,9 @@ hipError_t launch_batch_bf16(const ImgDev *d_descs, int n, int64_t total_tiles, 
     return launch_batch_t<BF16>(d_descs, n, total_tiles, mode, waves, th, grid, s);
 }
 
+hipError_t launch_batch_args_bf16(const BatchArgs &a, int mode, int waves, int th, int grid,
+                              hipStream_t s) {
+    return launch_batch_args_t<BF16>(a, mode, waves, th, grid, s);
+}
+
 }  // namespace convsep5

@@ -1,0 +1,119 @@
+// conv_loadgen.cpp -- open-loop request generator used to measure serving
+// latency (see conv_loadgen.h).  Built into libconvsep5_loadgen.so, which
+// calls libconvsep5 only through its public C ABI.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "conv_loadgen.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t ns_of(Clock::time_point t) {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(t.time_since_epoch())
+        .count();
+}
+
+// Busy-waits until t0 + offset_s; returns how late it is (s, >= 0).
+double wait_until(Clock::time_point t0, double offset_s) {
+    const auto target = t0 + std::chrono::duration_cast<Clock::duration>(
+                                 std::chrono::duration<double>(offset_s));
+    Clock::time_point now;
+    while ((now = Clock::now()) < target) {
+    }
+    return std::chrono::duration<double>(now - target).count();
+}
+
+bool args_ok(int32_t n, const double *arr, const void *const *in, void *const *out,
+             const float *k, const conv_image *imgs) {
+    if (n < 0) return false;
+    if (n == 0) return true;
+    return arr && in && out && k && imgs;
+}
+
+}  // namespace
+
+extern "C" {
+
+conv_status conv_loadgen_serve(conv_server *srv, int32_t n, const double *arrival_s,
+                               const void *const *d_in, void *const *d_out, const float *k,
+                               const conv_image *imgs, hipStream_t stream, uint64_t *tickets,
+                               double *lag_s) {
+    if (!srv || !tickets || !args_ok(n, arrival_s, d_in, d_out, k, imgs)) return CONV_EINVAL;
+    const auto t0 = Clock::now() + std::chrono::milliseconds(1);
+    for (int32_t i = 0; i < n; ++i) {
+        const double lag = wait_until(t0, arrival_s[i]);
+        if (lag_s) lag_s[i] = lag;
+        const conv_status st =
+            conv_serve_submit(srv, d_in[i], d_out[i], k + 5 * i, &imgs[i], stream, &tickets[i]);
+        if (st != CONV_OK) return st;
+    }
+    return CONV_OK;
+}
+
+conv_status conv_loadgen_direct(int32_t n, const double *arrival_s, const void *const *d_in,
+                                void *const *d_out, const float *k, const conv_image *imgs,
+                                int32_t n_streams, uint64_t *submit_ns, uint64_t *done_ns,
+                                double *lag_s) {
+    if (!submit_ns || !done_ns || n_streams < 1 || n_streams > 16 ||
+        !args_ok(n, arrival_s, d_in, d_out, k, imgs))
+        return CONV_EINVAL;
+    std::vector<hipStream_t> streams(n_streams, nullptr);
+    std::vector<hipEvent_t> events(n, nullptr);
+    conv_status rc = CONV_OK;
+    for (auto &s : streams)
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) rc = CONV_EHIP;
+    for (auto &e : events)
+        if (rc == CONV_OK && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            rc = CONV_EHIP;
+    // the watcher stamps completions of the requests enqueued so far
+    std::atomic<int32_t> enqueued{0};
+    std::atomic<bool> abort{false};
+    std::thread watcher([&] {
+        std::vector<int32_t> pending;
+        int32_t seen = 0, completed = 0;
+        while (completed < n && !abort.load()) {
+            const int32_t e = enqueued.load(std::memory_order_acquire);
+            for (; seen < e; ++seen) pending.push_back(seen);
+            for (size_t j = 0; j < pending.size();) {
+                const hipError_t q = hipEventQuery(events[pending[j]]);
+                if (q == hipErrorNotReady) {
+                    ++j;
+                    continue;
+                }
+                done_ns[pending[j]] = ns_of(Clock::now());
+                ++completed;
+                pending[j] = pending.back();
+                pending.pop_back();
+            }
+            if (pending.empty()) std::this_thread::yield();
+        }
+    });
+    const auto t0 = Clock::now() + std::chrono::milliseconds(1);
+    for (int32_t i = 0; i < n && rc == CONV_OK; ++i) {
+        const double lag = wait_until(t0, arrival_s[i]);
+        if (lag_s) lag_s[i] = lag;
+        hipStream_t s = streams[i % n_streams];
+        submit_ns[i] = ns_of(Clock::now());
+        rc = conv_sep5_1pass(d_in[i], d_out[i], k + 5 * i, &imgs[i], CONV_1PASS_FUSED, s);
+        if (rc == CONV_OK && hipEventRecord(events[i], s) != hipSuccess) rc = CONV_EHIP;
+        if (rc == CONV_OK) enqueued.store(i + 1, std::memory_order_release);
+    }
+    if (rc != CONV_OK) abort.store(true);
+    watcher.join();
+    for (auto s : streams)
+        if (s) hipStreamSynchronize(s);
+    for (auto e : events)
+        if (e) hipEventDestroy(e);
+    for (auto s : streams)
+        if (s) hipStreamDestroy(s);
+    return rc;
+}
+
+}  // extern "C"

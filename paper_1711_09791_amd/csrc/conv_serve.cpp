@@ -2,18 +2,27 @@
 // convolution.
 //
 // Requests (device-resident images of any size, each with its own taps) are
-// submitted without blocking.  One scheduler thread per server:
-//   1. retires launches whose completion event has fired (frees their slots
-//      and HBM budget, stamps their tickets done);
-//   2. while a launch stream is idle, admits queued requests in arrival order
-//      as long as a slot is free and their footprint (input + output bytes)
-//      fits the budget, up to max_batch requests of one dtype, and enqueues
-//      them as ONE persistent batch launch on that stream, followed by an
-//      event;
-//   3. waits for new work or polls the events of the launches in flight.
+// submitted without blocking.  One scheduler thread per server loops over:
+//   1. retire: launches whose completion event has fired free their slots and
+//      HBM budget and stamp their tickets done;
+//   2. admit: while a launch stream is idle, queued requests are taken in
+//      arrival order as long as a slot is free and their footprint (input +
+//      output bytes) fits the budget, up to max_batch requests of one dtype
+//      and max_batch_bytes per launch (so large frames run alone and small
+//      ones share launches);
+//   3. launch: each admitted group becomes ONE persistent batch launch on its
+//      stream, after a wait on the producers' events, followed by a
+//      completion event;
+//   4. poll the in-flight events, or spin briefly and then sleep when idle.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
-// same batch-kernel tile code as a lone call, so it is bitwise identical.
+// same tile code on the same values as a lone call, so it is bitwise
+// identical.
+//
+// Locking: the mutex guards what submitters and pollers touch (queue, ticket
+// table, event pool, statistics) and the budget counters.  Streams and the
+// list of in-flight launches belong to the scheduler thread, and every HIP
+// call of the scheduler runs without the lock.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +32,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "conv_common.h"
@@ -39,6 +49,8 @@ uint64_t now_ns() {
 
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3 };
 
+constexpr uint64_t kSpinIdleNs = 2000000;  // scheduler spins 2 ms after going idle
+
 struct Req {
     uint64_t ticket = 0;
     const void *in = nullptr;
@@ -49,6 +61,7 @@ struct Req {
     conv_req_times t{};
     int state = QUEUED;
     hipEvent_t ready = nullptr;  // recorded on the producer stream at submit
+    hipStream_t producer = nullptr;
 };
 
 struct Launch {
@@ -61,54 +74,37 @@ struct Launch {
 }  // namespace
 
 struct conv_server {
+    // fixed after creation
     conv_serve_cfg cfg{};
     int device = 0;
     std::vector<hipStream_t> streams;
-    std::vector<char> stream_busy;
-    std::vector<hipEvent_t> event_pool;   // launch-completion events
-    std::vector<hipEvent_t> ready_pool;   // producer-stream events of requests
+    // scheduler thread only
+    std::vector<Launch> inflight;
+    // shared, guarded by mu
     std::mutex mu;
     std::condition_variable cv;       // new work or stop
-    std::condition_variable idle_cv;  // queue and in-flight both empty
+    std::condition_variable idle_cv;  // nothing queued or in flight
     std::deque<Req *> queue;
     std::unordered_map<uint64_t, Req *> reqs;
-    std::vector<Launch> inflight;
+    std::vector<hipEvent_t> ready_pool;  // producer-stream events
+    std::vector<hipEvent_t> event_pool;  // launch-completion events
+    std::vector<char> stream_busy;
     uint64_t bytes_in_flight = 0;
     int slots_in_flight = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool idle = true;
     conv_serve_stats stats{};
     std::thread th;
 
     void run();
-    void retire_locked();
-    void launch_locked();
+    std::vector<Launch> admit_locked();
+    conv_status enqueue(Launch &L, hipEvent_t done_ev);
 };
 
-void conv_server::retire_locked() {
-    for (size_t i = 0; i < inflight.size();) {
-        Launch &L = inflight[i];
-        const hipError_t q = hipEventQuery(L.ev);
-        if (q == hipErrorNotReady) {
-            ++i;
-            continue;
-        }
-        const uint64_t t = now_ns();
-        for (Req *r : L.reqs) {
-            r->t.done_ns = t;
-            r->state = q == hipSuccess ? DONE : FAILED;
-        }
-        if (q == hipSuccess) stats.completed += L.reqs.size();
-        else stats.failed += L.reqs.size();
-        bytes_in_flight -= L.bytes;
-        slots_in_flight -= (int)L.reqs.size();
-        stream_busy[L.stream] = 0;
-        event_pool.push_back(L.ev);
-        inflight.erase(inflight.begin() + i);
-    }
-}
-
-void conv_server::launch_locked() {
+// Takes admissible requests off the queue (caller holds mu).
+std::vector<Launch> conv_server::admit_locked() {
+    std::vector<Launch> out;
     while (!queue.empty()) {
         int s = -1;
         for (int i = 0; i < (int)streams.size(); ++i)
@@ -116,104 +112,176 @@ void conv_server::launch_locked() {
                 s = i;
                 break;
             }
-        if (s < 0) return;
+        if (s < 0) break;
         Launch L;
         L.stream = s;
         const int dtype = queue.front()->img.dtype;
+        const uint64_t cap = cfg.max_batch_bytes ? cfg.max_batch_bytes : ~(uint64_t)0;
         while (!queue.empty() && (int)L.reqs.size() < cfg.max_batch &&
                slots_in_flight + 1 <= cfg.max_slots &&
-               bytes_in_flight + L.bytes + queue.front()->footprint <= cfg.hbm_budget_bytes &&
-               queue.front()->img.dtype == dtype) {
+               bytes_in_flight + queue.front()->footprint <= cfg.hbm_budget_bytes &&
+               queue.front()->img.dtype == dtype &&
+               (L.reqs.empty() || L.bytes + queue.front()->footprint <= cap)) {
             Req *r = queue.front();
             queue.pop_front();
             L.reqs.push_back(r);
             L.bytes += r->footprint;
+            bytes_in_flight += r->footprint;
             slots_in_flight += 1;
         }
-        if (L.reqs.empty()) return;  // head does not fit yet: wait for a retirement
-        bytes_in_flight += L.bytes;
-        const int n = (int)L.reqs.size();
-        std::vector<const void *> ins(n);
-        std::vector<void *> outs(n);
-        std::vector<float> ks(5 * n);
-        std::vector<conv_image> imgs(n);
-        const uint64_t t_admit = now_ns();
-        for (int i = 0; i < n; ++i) {
-            Req *r = L.reqs[i];
-            ins[i] = r->in;
-            outs[i] = r->out;
-            for (int j = 0; j < 5; ++j) ks[5 * i + j] = r->k[j];
-            imgs[i] = r->img;
-            r->t.admit_ns = t_admit;
-            r->t.batch_size = n;
+        if (L.reqs.empty()) break;  // the head does not fit yet: wait for a retirement
+        stream_busy[s] = 1;
+        const uint64_t t = now_ns();
+        for (Req *r : L.reqs) {
+            r->t.admit_ns = t;
+            r->t.batch_size = (int32_t)L.reqs.size();
             r->t.stream = s;
             r->state = INFLIGHT;
         }
-        const conv_tile_cfg tc = get_cfg(dtype, 1);
-        std::vector<ImgDev> descs;
-        int64_t total = 0;
-        int dt = 0;
-        conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
-                                     CONV_1PASS_FUSED, tc, &descs, &total, &dt);
-        // the launch starts only after each request's producer work
-        for (Req *r : L.reqs) {
-            if (st == CONV_OK && hipStreamWaitEvent(streams[s], r->ready, 0) != hipSuccess)
-                st = CONV_EHIP;
-            ready_pool.push_back(r->ready);
-            r->ready = nullptr;
-        }
-        if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, streams[s]);
         if (event_pool.empty()) {
             hipEvent_t e = nullptr;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) st = CONV_EHIP;
-            else event_pool.push_back(e);
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess)
+                event_pool.push_back(e);
         }
-        if (st == CONV_OK) {
+        if (!event_pool.empty()) {
             L.ev = event_pool.back();
             event_pool.pop_back();
-            if (hipEventRecord(L.ev, streams[s]) != hipSuccess) {
-                event_pool.push_back(L.ev);
-                st = CONV_EHIP;
-            }
         }
-        const uint64_t t_launch = now_ns();
-        if (st != CONV_OK) {
-            for (Req *r : L.reqs) {
-                r->t.launch_ns = r->t.done_ns = t_launch;
-                r->state = FAILED;
-            }
-            stats.failed += L.reqs.size();
-            bytes_in_flight -= L.bytes;
-            slots_in_flight -= n;
-            continue;
-        }
-        for (Req *r : L.reqs) r->t.launch_ns = t_launch;
-        stream_busy[s] = 1;
-        stats.launches += 1;
         stats.max_bytes_in_flight = std::max<uint64_t>(stats.max_bytes_in_flight, bytes_in_flight);
         stats.max_slots_in_flight = std::max(stats.max_slots_in_flight, slots_in_flight);
-        stats.max_batch = std::max(stats.max_batch, n);
-        inflight.push_back(std::move(L));
-        stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)inflight.size());
+        stats.max_batch = std::max(stats.max_batch, (int32_t)L.reqs.size());
+        out.push_back(std::move(L));
     }
+    return out;
+}
+
+// Enqueues one admitted group on its stream (no lock held).
+conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
+    if (!done_ev) return CONV_EHIP;
+    const int n = (int)L.reqs.size();
+    const int dtype = L.reqs[0]->img.dtype;
+    std::vector<const void *> ins(n);
+    std::vector<void *> outs(n);
+    std::vector<float> ks(5 * n);
+    std::vector<conv_image> imgs(n);
+    for (int i = 0; i < n; ++i) {
+        const Req *r = L.reqs[i];
+        ins[i] = r->in;
+        outs[i] = r->out;
+        for (int j = 0; j < 5; ++j) ks[5 * i + j] = r->k[j];
+        imgs[i] = r->img;
+    }
+    hipStream_t s = streams[L.stream];
+    const conv_tile_cfg tc = get_cfg(dtype, 1);
+    std::vector<ImgDev> descs;
+    int64_t total = 0;
+    int dt = 0;
+    conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
+                                 CONV_1PASS_FUSED, tc, &descs, &total, &dt);
+    // The launch starts only after each request's producer work.  Events
+    // recorded on one stream complete in order, so waiting on the latest
+    // request of each producer stream covers the earlier ones.
+    std::vector<std::pair<hipStream_t, hipEvent_t>> last;
+    for (Req *r : L.reqs) {
+        if (!r->ready) continue;  // producer_wait = 0
+        bool found = false;
+        for (auto &pe : last)
+            if (pe.first == r->producer) {
+                pe.second = r->ready;
+                found = true;
+            }
+        if (!found) last.emplace_back(r->producer, r->ready);
+    }
+    for (auto &pe : last)
+        if (st == CONV_OK && hipStreamWaitEvent(s, pe.second, 0) != hipSuccess) st = CONV_EHIP;
+    if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
+    if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
+    return st;
 }
 
 void conv_server::run() {
     hipSetDevice(device);
-    std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        retire_locked();
-        launch_locked();
-        if (queue.empty() && inflight.empty()) {
-            idle_cv.notify_all();
-            if (stop) break;
-            cv.wait(lk);
+        // 1. retire finished launches (event queries without the lock)
+        std::vector<std::pair<Launch, hipError_t>> finished;
+        for (size_t i = 0; i < inflight.size();) {
+            const hipError_t q = hipEventQuery(inflight[i].ev);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            finished.emplace_back(std::move(inflight[i]), q);
+            inflight.erase(inflight.begin() + i);
+        }
+        const uint64_t t_done = now_ns();
+        std::vector<Launch> admitted;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            for (auto &fq : finished) {
+                Launch &L = fq.first;
+                for (Req *r : L.reqs) {
+                    r->t.done_ns = t_done;
+                    r->state = fq.second == hipSuccess ? DONE : FAILED;
+                }
+                if (fq.second == hipSuccess) stats.completed += L.reqs.size();
+                else stats.failed += L.reqs.size();
+                bytes_in_flight -= L.bytes;
+                slots_in_flight -= (int)L.reqs.size();
+                stream_busy[L.stream] = 0;
+                event_pool.push_back(L.ev);
+            }
+            // 2. admit
+            admitted = admit_locked();
+        }
+        // 3. launch (no lock)
+        std::vector<conv_status> rc(admitted.size());
+        for (size_t i = 0; i < admitted.size(); ++i) rc[i] = enqueue(admitted[i], admitted[i].ev);
+        const uint64_t t_launch = now_ns();
+        {
+            std::lock_guard<std::mutex> g(mu);
+            for (size_t i = 0; i < admitted.size(); ++i) {
+                Launch &L = admitted[i];
+                for (Req *r : L.reqs) {
+                    if (r->ready) ready_pool.push_back(r->ready);
+                    r->ready = nullptr;
+                    r->t.launch_ns = t_launch;
+                }
+                if (rc[i] != CONV_OK) {
+                    for (Req *r : L.reqs) {
+                        r->t.done_ns = t_launch;
+                        r->state = FAILED;
+                    }
+                    stats.failed += L.reqs.size();
+                    bytes_in_flight -= L.bytes;
+                    slots_in_flight -= (int)L.reqs.size();
+                    stream_busy[L.stream] = 0;
+                    if (L.ev) event_pool.push_back(L.ev);
+                    continue;
+                }
+                stats.launches += 1;
+                inflight.push_back(std::move(L));
+            }
+            stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)inflight.size());
+        }
+        // 4. wait
+        if (!inflight.empty()) {
+            std::this_thread::yield();
             continue;
         }
-        // Work is on the device: poll its events without holding the lock.
-        lk.unlock();
-        std::this_thread::yield();
-        lk.lock();
+        std::unique_lock<std::mutex> lk(mu);
+        if (!queue.empty()) continue;
+        idle = true;
+        idle_cv.notify_all();
+        if (stop) break;
+        // Stay awake a little for the next arrival (a futex wake-up costs tens
+        // of microseconds), then sleep until a submit.
+        const uint64_t idle_from = now_ns();
+        while (queue.empty() && !stop && now_ns() - idle_from < kSpinIdleNs) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        }
+        if (queue.empty() && !stop) cv.wait(lk);
     }
 }
 
@@ -224,7 +292,8 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
     if (!cfg || !srv) return set_error(CONV_EINVAL, "NULL argument");
     *srv = nullptr;
     if (cfg->hbm_budget_bytes == 0 || cfg->max_slots < 1 || cfg->n_streams < 1 ||
-        cfg->n_streams > 16 || cfg->max_batch < 1)
+        cfg->n_streams > 16 || cfg->max_batch < 1 ||
+        (cfg->producer_wait != 0 && cfg->producer_wait != 1))
         return set_error(CONV_EINVAL, "bad server configuration");
     int prev = 0;
     hipGetDevice(&prev);
@@ -254,6 +323,7 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
 
 conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, const float k[5],
                               const conv_image *img, hipStream_t stream, uint64_t *ticket) {
+    const uint64_t t_submit = now_ns();
     clear_error();
     if (!srv || !ticket || !k) return set_error(CONV_EINVAL, "NULL argument");
     Layout L;
@@ -269,7 +339,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
         return set_error(CONV_ENOMEM, "footprint %llu exceeds the budget %llu",
                          (unsigned long long)fp, (unsigned long long)srv->cfg.hbm_budget_bytes);
     hipEvent_t ready = nullptr;
-    if (!L.empty) {
+    if (!L.empty && srv->cfg.producer_wait) {
         {
             std::lock_guard<std::mutex> g(srv->mu);
             if (!srv->ready_pool.empty()) {
@@ -290,12 +360,13 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     }
     auto *r = new Req();
     r->ready = ready;
+    r->producer = stream;
     r->in = d_in;
     r->out = d_out;
     for (int i = 0; i < 5; ++i) r->k[i] = k[i];
     r->img = *img;
     r->footprint = fp;
-    r->t.submit_ns = now_ns();
+    r->t.submit_ns = t_submit;
     {
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->stop) {
@@ -312,6 +383,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             srv->stats.completed += 1;
         } else {
             srv->queue.push_back(r);
+            srv->idle = false;
         }
         *ticket = r->ticket;
     }
@@ -324,16 +396,16 @@ conv_status conv_serve_poll(conv_server *srv, uint64_t ticket, conv_req_times *t
     if (!srv) return set_error(CONV_EINVAL, "NULL server");
     std::lock_guard<std::mutex> g(srv->mu);
     auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end()) return set_error(CONV_ENOTFOUND, "unknown ticket %llu",
-                                                (unsigned long long)ticket);
+    if (it == srv->reqs.end())
+        return set_error(CONV_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     Req *r = it->second;
     if (r->state == QUEUED || r->state == INFLIGHT) return CONV_EAGAIN;
     if (t) *t = r->t;
     const int state = r->state;
     srv->reqs.erase(it);
     delete r;
-    if (state == FAILED) return set_error(CONV_EHIP, "the launch of ticket %llu failed",
-                                          (unsigned long long)ticket);
+    if (state == FAILED)
+        return set_error(CONV_EHIP, "the launch of ticket %llu failed", (unsigned long long)ticket);
     return CONV_OK;
 }
 
@@ -342,7 +414,7 @@ conv_status conv_serve_drain(conv_server *srv) {
     if (!srv) return set_error(CONV_EINVAL, "NULL server");
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->cv.notify_one();
-    srv->idle_cv.wait(lk, [srv] { return srv->queue.empty() && srv->inflight.empty(); });
+    srv->idle_cv.wait(lk, [srv] { return srv->idle; });
     return CONV_OK;
 }
 

@@ -16,16 +16,18 @@ namespace {
 
 std::vector<conv_tile_cfg> candidates(int kind) {
     std::vector<conv_tile_cfg> c;
-    const int ths[] = {8, 16, 32, 64, 128};
+    const int ths[] = {4, 8, 16, 32, 64};
     const int waves[] = {1, 2, 4};
-    if (kind == 0) {
-        for (int th : ths)
-            for (int w : waves) c.push_back({th, w, 0});
-    } else {
-        const int persist[] = {2, 4, 8, 16};
-        for (int th : ths)
-            for (int w : waves)
-                for (int p : persist) c.push_back({th, w, p});
+    for (int x = 0; x < 2; ++x) {
+        if (kind == 0) {
+            for (int th : ths)
+                for (int w : waves) c.push_back({th, w, 0, x});
+        } else {
+            const int persist[] = {4, 8, 16};
+            for (int th : ths)
+                for (int w : waves)
+                    for (int p : persist) c.push_back({th, w, p, x});
+        }
     }
     return c;
 }

@@ -64,14 +64,16 @@ def batch_shapes(seed: int, n: int) -> list[tuple[int, int]]:
     return [(int(h), int(w)) for h, w in hw]
 
 
-def serving_stream(seed_arrival: int, seed_size: int, n: int, rate_per_s: float):
-    """Poisson request stream: (arrival offsets in s, (rows, cols) per request)."""
+def serving_stream(seed_arrival: int, seed_size: int, n: int, rate_per_s: float,
+                   sizes=SERVE_SIZES):
+    """Poisson request stream: (arrival offsets in s, (rows, cols) per request),
+    sizes drawn uniformly from `sizes`."""
     ra = np.random.default_rng(seed_arrival)
     rs = np.random.default_rng(seed_size)
     gaps = ra.exponential(1.0 / rate_per_s, size=n)
     arrivals = np.cumsum(gaps) - gaps[0]
-    idx = rs.integers(0, len(SERVE_SIZES), size=n)
-    return arrivals, [SERVE_SIZES[i] for i in idx]
+    idx = rs.integers(0, len(sizes), size=n)
+    return arrivals, [tuple(sizes[i]) for i in idx]
 
 
 def to_storage(img_f32: np.ndarray, dtype: str) -> np.ndarray:

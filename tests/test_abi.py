@@ -16,8 +16,8 @@ pytestmark = pytest.mark.skipif(not os.path.exists(cs.LIB_PATH),
                                 reason="libconvsep5.so not built")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(conv_[a-z0-9_]+)\s*\(",
                                  text, flags=re.M)))
@@ -36,6 +36,19 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), name
     assert "gfx950" in cs.conv_version()
+
+
+def test_loadgen_library_exports_its_header():
+    hdr = os.path.join(ROOT, "include", "conv_loadgen.h")
+    names = declared_functions(hdr)
+    assert set(names) == set(cs.LOADGEN_EXPORTS)
+    G = cs.loadgen_lib()
+    for name in names:
+        assert hasattr(G, name), name
+    # argument validation happens before any HIP call
+    assert G.conv_loadgen_serve(None, 1, None, None, None, None, None, None, None, None) == cs.CONV_EINVAL
+    assert G.conv_loadgen_direct(-1, None, None, None, None, None, 1, None, None, None) == cs.CONV_EINVAL
+    assert G.conv_loadgen_direct(1, None, None, None, None, None, 0, None, None, None) == cs.CONV_EINVAL
 
 
 def img(planes=3, rows=16, cols=16, dtype=0, pitch=0, plane_stride=0):
@@ -147,9 +160,11 @@ def test_tile_cfg_validation_and_roundtrip():
 def test_serve_config_validation():
     L = cs.lib()
     h = ctypes.c_void_p()
-    for cfg in (cs.conv_serve_cfg(0, 4, 2, 8, -1), cs.conv_serve_cfg(1 << 30, 0, 2, 8, -1),
-                cs.conv_serve_cfg(1 << 30, 4, 0, 8, -1), cs.conv_serve_cfg(1 << 30, 4, 17, 8, -1),
-                cs.conv_serve_cfg(1 << 30, 4, 2, 0, -1)):
+    for cfg in (cs.conv_serve_cfg(0, 4, 2, 8, -1, 0, 1), cs.conv_serve_cfg(1 << 30, 0, 2, 8, -1, 0, 1),
+                cs.conv_serve_cfg(1 << 30, 4, 0, 8, -1, 0, 1),
+                cs.conv_serve_cfg(1 << 30, 4, 17, 8, -1, 0, 1),
+                cs.conv_serve_cfg(1 << 30, 4, 2, 0, -1, 0, 1),
+                cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 2)):
         assert L.conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == cs.CONV_EINVAL
     assert L.conv_serve_poll(None, 1, None) == cs.CONV_EINVAL
     assert L.conv_serve_destroy(None) == cs.CONV_OK

@@ -131,14 +131,15 @@ def test_every_batch_tile_config_is_bitwise_identical_and_tuner_runs():
     base = [gu.nan_like(a) for a in ins]
     cs.conv_sep5_batch(ins, base, ks)
     try:
-        for th in (4, 16, 64, 128):
+        for th in (4, 8, 16, 64, 128):
             for w in (1, 2, 4):
                 for p in (1, 4, 16):
-                    cs.conv_set_tile_cfg(0, 1, th, w, p)
-                    outs = [gu.nan_like(a) for a in ins]
-                    cs.conv_sep5_batch(ins, outs, ks)
-                    for o, b in zip(outs, base):
-                        assert torch.equal(o, b), (th, w, p)
+                    for x in (0, 1):
+                        cs.conv_set_tile_cfg(0, 1, th, w, p, x)
+                        outs = [gu.nan_like(a) for a in ins]
+                        cs.conv_sep5_batch(ins, outs, ks)
+                        for o, b in zip(outs, base):
+                            assert torch.equal(o, b), (th, w, p, x)
         best, ms = cs.conv_tune(cs.KIND_BATCH, ins, base, ks, reps=2)
         assert best.rows_per_tile >= 1 and ms > 0
         best0, ms0 = cs.conv_tune(cs.KIND_IMAGE, ins[:1], base[:1], ks[:1], reps=2)
@@ -148,5 +149,6 @@ def test_every_batch_tile_config_is_bitwise_identical_and_tuner_runs():
         for o, b in zip(outs, base):
             assert torch.equal(o, b)
     finally:
-        cs.conv_set_tile_cfg(0, 1, orig.rows_per_tile, orig.waves_per_wg, orig.persist_wgs_per_cu)
-        cs.conv_set_tile_cfg(0, 0, orig0.rows_per_tile, orig0.waves_per_wg)
+        cs.conv_set_tile_cfg(0, 1, orig.rows_per_tile, orig.waves_per_wg, orig.persist_wgs_per_cu,
+                             orig.xcd_slabs)
+        cs.conv_set_tile_cfg(0, 0, orig0.rows_per_tile, orig0.waves_per_wg, 0, orig0.xcd_slabs)

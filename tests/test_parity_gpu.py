@@ -76,14 +76,15 @@ def test_every_tile_shape_is_bitwise_identical():
     orig = cs.conv_get_tile_cfg(0, 0)
     try:
         base = {f: gu.to_host_bits(gu.run(f, a, k)) for f in FORMS}
-        for th in (1, 3, 8, 17, 64, 200):
+        for th in (1, 3, 4, 8, 17, 64, 200):
             for w in (1, 2, 4):
-                cs.conv_set_tile_cfg(0, 0, th, w)
-                for f in FORMS:
-                    got = gu.to_host_bits(gu.run(f, a, k))
-                    assert np.array_equal(got, base[f]), (th, w, f)
+                for x in (0, 1):
+                    cs.conv_set_tile_cfg(0, 0, th, w, 0, x)
+                    for f in FORMS:
+                        got = gu.to_host_bits(gu.run(f, a, k))
+                        assert np.array_equal(got, base[f]), (th, w, x, f)
     finally:
-        cs.conv_set_tile_cfg(0, 0, orig.rows_per_tile, orig.waves_per_wg)
+        cs.conv_set_tile_cfg(0, 0, orig.rows_per_tile, orig.waves_per_wg, 0, orig.xcd_slabs)
     gu.check_f32(base["fused"], gu.oracle_of(host, k))
 
 

@@ -118,3 +118,24 @@ def test_errors_and_ticket_lifecycle():
             srv.poll(t)  # reported once, then forgotten
     finally:
         srv.destroy()
+
+
+def test_no_producer_wait_mode_after_sync():
+    """producer_wait = 0: the caller synchronises its inputs before submitting."""
+    import torch
+
+    torch.manual_seed(3)
+    reqs = _requests(16, seed=4, sizes=((480, 640), (720, 1280)))
+    outs = [gu.nan_like(a) for a, _ in reqs]
+    torch.cuda.synchronize()
+    srv = cs.conv_serve_create(1 << 30, max_slots=16, n_streams=2, max_batch=8,
+                               max_batch_bytes=64 << 20, producer_wait=False)
+    try:
+        tickets = [srv.submit(a, o, k) for (a, k), o in zip(reqs, outs)]
+        _wait_all(srv, tickets)
+    finally:
+        srv.destroy()
+    for (a, k), o in zip(reqs, outs):
+        r = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, r, k)
+        assert torch.equal(o, r)
