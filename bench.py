@@ -86,26 +86,22 @@ def traffic_for(form: str):
 
 
 def timed(torch, fn, steps, warmup):
-    """Total ms over `steps` calls and sorted per-call ms, from HIP events on
-    torch's current stream (the stream every call here launches on)."""
+    """ms over `steps` back-to-back calls, from a pair of HIP events recorded
+    on torch's current stream (the stream every call here launches on) around
+    the whole timed region, bracketed by device synchronisation.  No event
+    sits between the launches, so total / steps is the average launch
+    duration including only the GPU's own gap between consecutive kernels."""
     for i in range(warmup):
         fn(i)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
     for i in range(steps):
-        ev[i][0].record()
         fn(i)
-        ev[i][1].record()
     t1.record()
     torch.cuda.synchronize()
-    total = t0.elapsed_time(t1)
-    per = sorted(a.elapsed_time(b) for a, b in ev)
-    return total, per
+    return t0.elapsed_time(t1)
 
 
 def check(cs, st):
@@ -141,22 +137,21 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
     alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz}
     res = {}
     for name in forms:
-        total, per = timed(torch, steps_fn[name], args.steps, args.warmup)
-        avg = sum(per) / len(per)
+        total = timed(torch, steps_fn[name], args.steps, args.warmup)
+        avg = total / args.steps
         nbytes = alg_bytes[name] * P * R * C
         res[name] = {
-            "ms_per_step": total / args.steps,
-            "avg_launch_ms": avg,
-            "median_launch_ms": per[len(per) // 2],
-            "mpix_per_s": (R * C) / (total / args.steps * 1e-3) / 1e6,
+            "ms_per_step": avg,
+            "avg_launch_ms": avg if name != "2pass" else avg / 2,
+            "launches_per_step": 2 if name == "2pass" else 1,
+            "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
             "alg_bytes_per_step": nbytes,
             "alg_GBps": nbytes / (avg * 1e-3) / 1e9,
             "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
         }
     if "fused" in res and getattr(args, "warm", False):
         fn = lambda i: check(cs, L.conv_sep5_1pass(pin[0], pout[0], kk, pimg, 0, hs))  # noqa: E731
-        _, per = timed(torch, fn, args.steps, args.warmup)
-        res["fused"]["warm_same_buffers_avg_launch_ms"] = sum(per) / len(per)
+        res["fused"]["warm_same_buffers_avg_launch_ms"] = timed(torch, fn, args.steps, args.warmup) / args.steps
     if "fused" in res and "copy" in res:
         res["fused"]["frac_of_copy"] = res["copy"]["avg_launch_ms"] / res["fused"]["avg_launch_ms"]
     eq = None
@@ -179,12 +174,12 @@ def bench_batch(torch, cs, synth, args):
     pix = sum(h * w for h, w in shapes)
     nbytes = 24 * pix
     steps = max(10, args.steps // 10)
-    t_eager, _ = timed(torch, lambda i: cs.conv_sep5_batch(ins, outs, ks), steps, 3)
+    t_eager = timed(torch, lambda i: cs.conv_sep5_batch(ins, outs, ks), steps, 3)
     plan = cs.conv_batch_plan_create(ins, outs, ks)
-    t_graph, _ = timed(torch, lambda i: plan.launch(), steps, 3)
+    t_graph = timed(torch, lambda i: plan.launch(), steps, 3)
     plan.destroy()
-    t_lone, _ = timed(torch, lambda i: [cs.conv_sep5_1pass(a, o, k) for a, o, k in zip(ins, outs, ks)],
-                      steps, 3)
+    t_lone = timed(torch, lambda i: [cs.conv_sep5_1pass(a, o, k) for a, o, k in zip(ins, outs, ks)],
+                   steps, 3)
     cfg = cs.conv_get_tile_cfg(0, 1).as_dict()
     ms_e, ms_g, ms_l = t_eager / steps, t_graph / steps, t_lone / steps
     return {
