@@ -8,7 +8,7 @@
  *     B[p][y][x] = sum_{i=-2..2} sum_{j=-2..2} A[p][y+i][x+j] * k[i+2] * k[j+2]
  *
  * for every plane p and every pixel whose 5x5 neighbourhood lies inside the
- * image (2 <= y < rows-2, 2 <= x < cols-2; Section 4 starts the convolution at
+ * image (2 <= y < rows-2, 2 <= x < cols-2; Section 5 starts the convolution at
  * pixel (2,2) and ignores the edges).  Every other output pixel (the 2-pixel
  * frame) is written as +0.0.  The form is a correlation: k[0] weights the
  * neighbour at offset -2 (the tap order of the paper's listings in
@@ -21,7 +21,7 @@
  * forms perform the same operations on the same values, so their outputs are
  * bitwise identical; so are the batched, graph-replayed and served results
  * for the same image and taps.  The direct 25-tap mode (the paper's
- * single-pass arithmetic, Section 4.1, Eq. 2 / Eq. 3) rounds K[a][b] once
+ * single-pass arithmetic, Section 5.2, Eq. 2 / Eq. 3) rounds K[a][b] once
  * to FP32 on the host, runs a 5-term FMA chain per kernel row and adds the
  * five row partials pairwise.
  *
@@ -62,9 +62,9 @@ typedef enum {
 typedef enum { CONV_F32 = 0, CONV_F16 = 1, CONV_BF16 = 2 } conv_dtype;
 
 /*
- * Image descriptor (the paper's planes/rows/cols image record, Section 4.3,
- * with planar [plane][row][col] storage, Section 4.1 Eq. 2, and the flat
- * index p*rows*cols + r*cols + c of Section 4.4 generalised by strides).
+ * Image descriptor (the paper's planes/rows/cols image record, Section 5.3,
+ * with planar [plane][row][col] storage, Section 5.2 Eq. 2, and the flat
+ * index p*rows*cols + r*cols + c of Section 5.4 generalised by strides).
  * Element (p, y, x) lives at base + p*plane_stride + y*pitch + x, counted in
  * elements of `dtype`.  The same layout applies to the input and the output.
  *   planes       >= 0 (3 colour planes in the paper's workload)
@@ -92,13 +92,13 @@ enum {
 };
 
 /*
- * Two-pass form (Section 4.1, "two-pass algorithm"; Section 4.3 and 4.4
+ * Two-pass form (Section 5.1, "two-pass algorithm"; Section 5.3 and 5.4
  * listings): a row kernel filters every row of every plane horizontally into
  * the FP32 workspace `d_tmp`, then a column kernel filters it vertically into
  * `d_out`.  The two kernels are ordered on `stream` (the analogue of the
  * barrier between the passes).
  *   d_in, d_out  device images described by *img; d_out == d_in is allowed
- *                (the paper's in-place two-pass, Section 6) -- any other
+ *                (the paper's in-place two-pass, Section 7) -- any other
  *                partial overlap is CONV_EALIAS.
  *   d_tmp        FP32 workspace of planes*rows*cols floats, dense
  *                [plane][row][col]; must not overlap d_in or d_out.  NULL
@@ -111,7 +111,7 @@ conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp,
                             hipStream_t stream);
 
 /*
- * Single-pass form (Section 4.1 and Section 6, "single-pass without
+ * Single-pass form (Section 5.1 and Section 7, "single-pass without
  * copy-back": the result is written once to a separate output).  One kernel;
  * mode CONV_1PASS_FUSED keeps the row-filtered rows in registers, mode
  * CONV_1PASS_DIRECT25 evaluates the 25-term sum of Eq. 2.
@@ -126,7 +126,7 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
 /*
  * Many images of different sizes in ONE persistent kernel launch (the
  * device-side counterpart of the paper's task agglomeration over planes,
- * Section 5).  All images must share one dtype; each has its own taps.
+ * Section 6).  All images must share one dtype; each has its own taps.
  *   n            number of images (>= 0; 0 enqueues nothing)
  *   d_in, d_out  host arrays of n device pointers
  *   k            host array of n*5 FP32 taps (image i uses k[5i .. 5i+4])

@@ -10,7 +10,8 @@ only compiles it with gcc (on first use, if it is not built yet) and marshals
 numpy arrays through ctypes.
 
 Functions (all follow Eq. 1 of Section 1 with K = k k^T, the border rule of
-Section 4, and planes processed independently as in Section 4.3):
+Section 5's opening paragraph, and planes processed independently as in the
+per-plane driver of Section 5.3):
 
 ``conv5(A, k)``            single-pass (25-term) form in FP64.
 ``conv5_twopass(A, k)``    separable two-pass form in FP64.

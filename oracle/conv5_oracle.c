@@ -11,11 +11,11 @@
  *   - Eq. 1 (Section 1): B[y][x] = sum_i sum_j A[y+i][x+j] * K[i][j], written
  *     as a correlation (the kernel is not flipped), with the separable kernel
  *     K[i][j] = k_i * k_j (Section 1, right after Eq. 1), i, j in -2..2
- *     (width 5, Section 1 and Section 4).
- *   - Border convention (Section 4, opening paragraph): only pixels whose whole
+ *     (width 5: Section 1 and the 5x5 Gaussian of Section 4).
+ *   - Border convention (Section 5, opening paragraph): only pixels whose whole
  *     5x5 neighbourhood lies inside the image are convolved, starting at pixel
  *     (2,2).  The paper leaves the rest untouched; this oracle fixes it to 0.
- *   - Planes are independent (Section 4.3, the per-plane driver loop).
+ *   - Planes are independent (Section 5.3, the per-plane driver loop).
  *
  * All arithmetic is IEEE binary64.  The 16-bit helpers decode half and bfloat16
  * storage exactly and round binary64 results to those formats with
@@ -31,7 +31,7 @@
 #define R5 2 /* kernel radius: taps at offsets -2..2 */
 
 /*
- * Single-pass form (Section 4.1, Eq. 2 / Eq. 3): four nested loops, 25
+ * Single-pass form (Section 5.1; Eq. 2 / Eq. 3 of Section 5.2): four nested loops, 25
  * multiply-adds per interior pixel, K[a][b] = k[a] * k[b] evaluated in FP64.
  * A and B are dense [planes][rows][cols]; B is fully written.
  * nthreads <= 0 means "whatever OpenMP picks"; 1 means serial.
@@ -70,7 +70,7 @@ void oracle_conv5_direct(const double *A, double *B, const double *k,
 }
 
 /*
- * Two-pass form (Section 4.1, the separable algorithm): a horizontal 5-tap
+ * Two-pass form (Section 5.1, the separable algorithm): a horizontal 5-tap
  * pass into an auxiliary array, then a vertical 5-tap pass out of it.  The
  * horizontal pass covers every row, so that the vertical pass at rows 2, 3,
  * H-4 and H-3 reads filtered data.  aux must hold rows*cols doubles.

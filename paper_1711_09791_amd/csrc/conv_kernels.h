@@ -3,7 +3,7 @@
 //
 // Operation: Eq. 1 of arXiv 1711.09791 (Section 1) with K[i][j] = k_i k_j,
 // correlation form, computed on pixels whose 5x5 neighbourhood is inside the
-// image (Section 4); the 2-pixel frame is written as +0.0.
+// image (Section 5, opening paragraph); the 2-pixel frame is written as +0.0.
 //
 // Work decomposition (one wavefront = one tile):
 //   * a lane owns VEC = 16 bytes of consecutive columns of storage (4 FP32 or

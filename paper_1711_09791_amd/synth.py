@@ -4,8 +4,9 @@ This module only draws inputs; it holds none of the convolution's arithmetic.
 Both the HIP path and the FP64 oracle are fed from it.
 
 The paper's test images are not published: it states only that they are
-square, 3 colour planes, 1152^2 to 8748^2 (Section 3 and Section 4), and that
-the kernel is a 5x5 separable Gaussian (Section 3).  The generators below stand
+square, 3 colour planes, 1152^2 to 8748^2 (Section 4, Experimental Setup),
+and that the kernel is a 5x5 separable Gaussian (Section 4).  The generators
+below stand
 in for them:
 
 * pixels: uniform [0, 1) FP32 from numpy's PCG64 (multiples of 2^-24);
