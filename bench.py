@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sets", type=int, default=3, help="rotating buffer sets")
-    ap.add_argument("--forms", default="fused,2pass,direct25,copy")
+    ap.add_argument("--forms", default="fused,2pass,direct25,copy,1pass_copyback,2pass_inplace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, batch and serving measurements")
@@ -119,7 +119,9 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
     S = max(1, args.sets)
     ins = [base] + [base.clone() for _ in range(S - 1)]
     outs = [torch.empty_like(base) for _ in range(S)]
-    tmp = torch.empty(P * R * C, device=dev) if "2pass" in forms else None
+    tmp = torch.empty(P * R * C, device=dev) if ("2pass" in forms or "2pass_inplace" in forms) else None
+    for o in outs:  # the in-place forms work on the output buffers
+        o.copy_(base)
     L = cs.lib()
     img = cs.image_of(base)
     kk = (ctypes.c_float * 5)(*[float(v) for v in k])
@@ -129,12 +131,17 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
     ptmp = ctypes.c_void_p(tmp.data_ptr()) if tmp is not None else None
     pimg = ctypes.byref(img)
     steps_fn = {
+        # the paper's in-place variants (Section 7): copy-back single-pass, in-place two-pass
+        "1pass_copyback": lambda i: check(cs, L.conv_sep5_1pass(pout[i % S], pout[i % S], kk, pimg, 0, hs)),
+        "2pass_inplace": lambda i: check(cs, L.conv_sep5_2pass(pout[i % S], pout[i % S], ptmp, kk, pimg, hs)),
         "fused": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 0, hs)),
         "direct25": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 1, hs)),
         "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, pimg, hs)),
         "copy": lambda i: outs[i % S].copy_(ins[i % S]),
     }
-    alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz}
+    alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz,
+                 "1pass_copyback": 4 * esz, "2pass_inplace": 2 * esz + 8}
+    launches = {"2pass": 2, "2pass_inplace": 2, "1pass_copyback": 2}
     res = {}
     for name in forms:
         total = timed(torch, steps_fn[name], args.steps, args.warmup)
@@ -142,8 +149,8 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
         nbytes = alg_bytes[name] * P * R * C
         res[name] = {
             "ms_per_step": avg,
-            "avg_launch_ms": avg if name != "2pass" else avg / 2,
-            "launches_per_step": 2 if name == "2pass" else 1,
+            "avg_launch_ms": avg / launches.get(name, 1),
+            "launches_per_step": launches.get(name, 1),
             "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
             "alg_bytes_per_step": nbytes,
             "alg_GBps": nbytes / (avg * 1e-3) / 1e9,

@@ -71,7 +71,10 @@ typedef enum { CONV_F32 = 0, CONV_F16 = 1, CONV_BF16 = 2 } conv_dtype;
  *   rows, cols   >= 0 (any of planes/rows/cols == 0 means "nothing to do")
  *   pitch        elements between rows; 0 means cols; otherwise >= cols
  *   plane_stride elements between planes; 0 means rows*pitch; otherwise
- *                >= (rows-1)*pitch + cols
+ *                either >= (rows-1)*pitch + cols (planar), or >= cols with
+ *                (planes-1)*plane_stride + cols <= pitch: the planes' rows
+ *                side by side in one row (the row-interleaved "3R x C"
+ *                layout of Section 6).  Each plane keeps its own border.
  * The fast path needs 16-byte aligned base pointers and cols, pitch and
  * plane_stride that are multiples of 16/sizeof(element); other layouts run a
  * slower element-wise path with identical results.
@@ -115,8 +118,12 @@ conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp,
  * copy-back": the result is written once to a separate output).  One kernel;
  * mode CONV_1PASS_FUSED keeps the row-filtered rows in registers, mode
  * CONV_1PASS_DIRECT25 evaluates the 25-term sum of Eq. 2.
- *   d_in, d_out  device images described by *img; must not overlap
- *                (CONV_EALIAS).
+ *   d_in, d_out  device images described by *img.  d_out == d_in selects the
+ *                paper's single-pass WITH copy-back (Section 5.2, Section 7):
+ *                the result goes to stream-ordered scratch (hipMallocAsync /
+ *                hipFreeAsync on `stream`) and a copy kernel writes it over
+ *                the input -- 16 B per plane-pixel instead of 8.  Any other
+ *                overlap is CONV_EALIAS.
  *   k            5 FP32 taps (host array).
  */
 conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],

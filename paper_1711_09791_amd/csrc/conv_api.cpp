@@ -59,9 +59,15 @@ conv_status check_image(const conv_image *img, Layout *L) {
     const int64_t rows = img->rows, cols = img->cols, planes = img->planes;
     const int64_t min_ps = rows > 0 ? (rows - 1) * L->pitch + cols : 0;
     L->ps = img->plane_stride == 0 ? rows * L->pitch : img->plane_stride;
-    if (img->plane_stride != 0 && L->ps < min_ps)
-        return set_error(CONV_EINVAL, "plane_stride %lld < %lld", (long long)img->plane_stride,
-                         (long long)min_ps);
+    // Planes must not overlap: either one after another (planar), or side by
+    // side within each row (row-interleaved, the 3R x C layout).
+    const bool planar = L->ps >= min_ps;
+    const bool interleaved = L->ps >= cols && (planes - 1) * L->ps + cols <= L->pitch;
+    if (img->plane_stride != 0 && planes > 1 && !planar && !interleaved)
+        return set_error(CONV_EINVAL,
+                         "plane_stride %lld makes planes overlap (needs >= %lld, or planes "
+                         "side by side within a row of pitch %lld)",
+                         (long long)img->plane_stride, (long long)min_ps, (long long)L->pitch);
     if (L->ps > ((int64_t)1 << 50))
         return set_error(CONV_EINVAL, "plane_stride %lld too large", (long long)L->ps);
     L->empty = planes == 0 || rows == 0 || cols == 0;
@@ -342,14 +348,34 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
         return set_error(CONV_EINVAL, "mode %d is not FUSED or DIRECT25", mode);
     if (L.empty) return CONV_OK;
     if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
-    if (overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
-        return set_error(CONV_EALIAS, "input and output overlap");
+    const bool copy_back = d_in == (const void *)d_out;
+    if (!copy_back && overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
+        return set_error(CONV_EALIAS, "input and output partially overlap");
     const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    const int kmode = mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25;
     ImgDev d;
-    const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
-    hipError_t e = launch_image(d, img->dtype, mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
-                                cfg.waves_per_wg, nblocks, stream);
-    if (e != hipSuccess) return hip_error(e, "1pass kernel launch");
+    if (!copy_back) {
+        const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
+        hipError_t e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+        if (e != hipSuccess) return hip_error(e, "1pass kernel launch");
+        return CONV_OK;
+    }
+    // Single-pass with copy-back (the paper's in-place single-pass): convolve
+    // into stream-ordered scratch of the image's layout, then copy the result
+    // over the input.
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, (size_t)L.extent_bytes, stream);
+    if (e != hipSuccess)
+        return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)L.extent_bytes,
+                         hipGetErrorString(e));
+    int64_t nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg);
+    e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+    if (e == hipSuccess) {
+        nblocks = fill_desc(&d, scratch, d_out, nullptr, img, L, k, cfg);
+        e = launch_image(d, img->dtype, MODE_COPY, cfg.waves_per_wg, nblocks, stream);
+    }
+    (void)hipFreeAsync(scratch, stream);
+    if (e != hipSuccess) return hip_error(e, "1pass (copy-back) kernel launch");
     return CONV_OK;
 }
 

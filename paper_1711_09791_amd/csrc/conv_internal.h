@@ -11,7 +11,8 @@ enum Mode : int {
     MODE_FUSED = 0,     // row filter -> register window -> column filter
     MODE_DIRECT25 = 1,  // 25 multiply-adds per pixel (paper's single pass)
     MODE_ROWPASS = 2,   // two-pass, first kernel: input -> FP32 intermediate
-    MODE_COLPASS = 3    // two-pass, second kernel: FP32 intermediate -> output
+    MODE_COLPASS = 3,   // two-pass, second kernel: FP32 intermediate -> output
+    MODE_COPY = 4       // copy-back of the single-pass result (in -> out, same layout)
 };
 
 // Taps as the kernels read them: k for the separable forms, K = fl32(k_a k_b)

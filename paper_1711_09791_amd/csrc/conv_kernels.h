@@ -72,15 +72,17 @@ typedef _Float16 h2v __attribute__((ext_vector_type(2)));
 typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 // Two FP32 values -> one packed word of two 16-bit values (low half = a),
 // rounded to nearest even by the hardware converters (v_cvt_pk_f16_f32 /
-// v_cvt_pk_bf16_f32 on gfx950).
+// v_cvt_pk_bf16_f32 on gfx950).  Every 16-bit store goes through this pair
+// conversion: a lone float->half conversion lets the compiler fold it with
+// the last FMA of the filter into one mixed-precision FMA that rounds once,
+// straight to 16 bits, which skips the FP32 result and can differ from it by
+// one unit at ties.
 __device__ __forceinline__ uint32_t enc2(F16, float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, h2v));
 }
 __device__ __forceinline__ uint32_t enc2(BF16, float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, b2v));
 }
-__device__ __forceinline__ uint32_t enc(F16, float f) { return enc2(F16{}, f, 0.0f) & 0xffffu; }
-__device__ __forceinline__ uint32_t enc(BF16, float f) { return enc2(BF16{}, f, 0.0f) & 0xffffu; }
 
 // ---- buffer resources, DPP ----------------------------------------------
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
@@ -220,14 +222,16 @@ __device__ __forceinline__ void store_out(char *row, uint32_t rbytes, int x,
             for (int i = 0; i < 4; ++i) q[i] = enc2(D{}, o[2 * i], o[2 * i + 1]);
         }
         __builtin_amdgcn_raw_buffer_store_b128(q, rs, x * D::ESZ, 0, NT);
+    } else if constexpr (D::ESZ == 4) {
+#pragma unroll
+        for (int e = 0; e < D::VEC; ++e)
+            __builtin_amdgcn_raw_buffer_store_b32(enc(D{}, o[e]), rs, (x + e) * 4, 0, NT);
     } else {
 #pragma unroll
-        for (int e = 0; e < D::VEC; ++e) {
-            if constexpr (D::ESZ == 4)
-                __builtin_amdgcn_raw_buffer_store_b32(enc(D{}, o[e]), rs, (x + e) * 4, 0, NT);
-            else
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)enc(D{}, o[e]), rs, (x + e) * 2,
-                                                      0, NT);
+        for (int e = 0; e < D::VEC; e += 2) {
+            const uint32_t w = enc2(D{}, o[e], o[e + 1]);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w & 0xffffu), rs, (x + e) * 2, 0, NT);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w >> 16), rs, (x + e + 1) * 2, 0, NT);
         }
     }
 }
@@ -535,6 +539,38 @@ __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs
 #undef CONV_RSTEP
 }
 
+// ---- copy-back (single-pass result written back over the input) ------------------
+template <class D, bool AL>
+__device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, int y0, int y1,
+                                          int lane) {
+    constexpr int VEC = D::VEC;
+    const int x = xs + lane * VEC;
+    const char *sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+    char *dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
+    const int64_t stride = im.pitch * D::ESZ;
+    const uint32_t rbytes = (uint32_t)im.cols * D::ESZ;
+#pragma unroll 8
+    for (int y = y0; y < y1; ++y) {
+        const auto rs = row_rsrc(sbase + (int64_t)y * stride, rbytes);
+        const auto rd = row_rsrc(dbase + (int64_t)y * stride, rbytes);
+        if constexpr (AL) {
+            const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(v, rd, x * D::ESZ, 0, NT);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const int off = (x + e) * D::ESZ;
+                if constexpr (D::ESZ == 4)
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0), rd, off, 0, NT);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b16(
+                        __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0), rd, off, 0, NT);
+            }
+        }
+    }
+}
+
 // ---- tiles -----------------------------------------------------------------------
 // Logical tile lt = (plane, band, strip group), strip group fastest.  Wave
 // `wave` of the workgroup takes strip sg*WAVES + wave of the group.  TH > 0:
@@ -542,7 +578,9 @@ __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs
 template <class D, bool AL, int MODE, bool EDGE, int TH>
 __device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, int y0, int y1,
                                          int lane) {
-    if constexpr (MODE == MODE_ROWPASS) {
+    if constexpr (MODE == MODE_COPY) {
+        band_copy<D, AL>(im, plane, xs, y0, y1, lane);
+    } else if constexpr (MODE == MODE_ROWPASS) {
         if constexpr (TH > 0) {
             if (y1 - y0 == TH) {
                 band_rowpass_fixed<D, AL, EDGE, TH>(im, plane, xs, y0, lane);
@@ -576,7 +614,9 @@ __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave,
     // writes every row, so only columns matter there.)
     const bool col_edge = xs < 2 || xs + WAVE * D::VEC > im.cols - 2;
     const bool row_edge = MODE != MODE_ROWPASS && (y0 < 2 || y1 > im.rows - 2);
-    if (col_edge || row_edge)
+    if constexpr (MODE == MODE_COPY)
+        run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
+    else if (col_edge || row_edge)
         run_band<D, AL, MODE, true, TH>(im, plane, xs, y0, y1, lane);
     else
         run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
@@ -686,6 +726,7 @@ hipError_t launch_image_m(const ImgDev &im, int mode, int waves, int64_t nblocks
     case MODE_FUSED: return launch_image_w<D, AL, MODE_FUSED>(im, waves, nblocks, s);
     case MODE_DIRECT25: return launch_image_w<D, AL, MODE_DIRECT25>(im, waves, nblocks, s);
     case MODE_ROWPASS: return launch_image_w<D, AL, MODE_ROWPASS>(im, waves, nblocks, s);
+    case MODE_COPY: return launch_image_w<D, AL, MODE_COPY>(im, waves, nblocks, s);
     default: return launch_image_w<D, AL, MODE_COLPASS>(im, waves, nblocks, s);
     }
 }

@@ -73,6 +73,8 @@ def call2(i, a=A, b=B, t=0, k=K):
     dict(dtype=3), dict(dtype=-1), dict(planes=-1), dict(rows=-2), dict(cols=-5),
     dict(pitch=8), dict(rows=4, plane_stride=10), dict(rows=(1 << 30) + 1),
     dict(cols=(1 << 28) + 1),
+    dict(cols=16, pitch=48, plane_stride=15),   # interleaved planes overlapping
+    dict(cols=16, pitch=40, plane_stride=16),   # third plane runs past the row
 ])
 def test_1pass_rejects_bad_descriptor(bad):
     assert call1(img(**bad)) == cs.CONV_EINVAL
@@ -89,7 +91,7 @@ def test_1pass_rejects_null_and_mode():
 
 def test_1pass_alias_checks():
     n = 3 * 16 * 16 * 4
-    assert call1(img(), a=A, b=A) == cs.CONV_EALIAS
+    assert call1(img(), a=A, b=A + 4) == cs.CONV_EALIAS
     assert call1(img(), a=A, b=A + n - 4) == cs.CONV_EALIAS
     assert call1(img(), a=A + n - 4, b=A) == cs.CONV_EALIAS
 
@@ -204,3 +206,11 @@ def test_binding_rejects_mismatched_output_layout():
     big = torch.zeros(3, 10, 16)
     with pytest.raises(ValueError):
         cs.conv_sep5_batch([a], [big[:, :, :12]], [[1, 4, 6, 4, 1]])
+
+
+def test_row_interleaved_planes_accepted():
+    # 3R x C: each row holds the three planes' rows side by side (no GPU call:
+    # the empty output pointer check fails after layout validation)
+    i = img(planes=3, rows=16, cols=16, pitch=48, plane_stride=16)
+    assert call1(i, b=0) == cs.CONV_EINVAL
+    assert "NULL" in cs.conv_last_error()

@@ -111,17 +111,19 @@ def test_pitched_and_offset_layouts():
             assert np.all(bo[mask] == 12345.0), (f, pr, pc, "wrote outside the image")
 
 
-def test_unaligned_pointer_matches_aligned():
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_unaligned_pointer_matches_aligned(dtype):
+    """The element-wise path (misaligned base) is bitwise equal to the vector path."""
     torch = _torch()
     host = synth.image(61, 3, 90, 512)
     k = synth.taps_random(62)
-    a = gu.to_device(host)
-    flat = torch.zeros(host.size + 1, device="cuda")
+    a = gu.to_device(synth.to_storage(host, dtype), dtype)
+    flat = torch.zeros(host.size + 1, dtype=a.dtype, device="cuda")
     flat[1:] = a.reshape(-1)
-    au = flat[1:].view(3, 90, 512)          # 4-byte offset: not 16-byte aligned
+    au = flat[1:].view(3, 90, 512)          # one-element offset: not 16-byte aligned
     for f in FORMS:
         ref = gu.to_host_bits(gu.run(f, a, k))
-        fo = torch.full((host.size + 1,), float("nan"), device="cuda")
+        fo = torch.full((host.size + 1,), float("nan"), dtype=a.dtype, device="cuda")
         got = gu.run(f, au, k, out=fo[1:].view(3, 90, 512))
         assert np.array_equal(gu.to_host_bits(got), ref), f
 
@@ -209,3 +211,46 @@ def test_full_size_sampled_rows():
         assert torch.all(o[:, :2, :] == 0) and torch.all(o[:, -2:, :] == 0)
         assert torch.all(o[:, :, :2] == 0) and torch.all(o[:, :, -2:] == 0)
         assert torch.isfinite(o).all()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_1pass_copy_back_in_place(dtype):
+    """out == in: the single-pass with copy-back gives the out-of-place result,
+    in place, and touches nothing outside the image (pitched layout)."""
+    torch = _torch()
+    P, R, C = 3, 70, 520
+    host32 = synth.image(111, P, R, C)
+    bits = synth.to_storage(host32, dtype)
+    k = synth.taps_random(112)
+    a = gu.to_device(bits, dtype)
+    for mode in (cs.CONV_1PASS_FUSED, cs.CONV_1PASS_DIRECT25):
+        ref = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, ref, k, mode)
+        big = torch.zeros(P, R + 2, C + 8, dtype=a.dtype, device="cuda")
+        big.fill_(3.0)
+        v = big[:, 1:R + 1, 4:C + 4]
+        v.copy_(a)
+        cs.conv_sep5_1pass(v, v, k, mode)
+        assert torch.equal(v.view(torch.int16) if dtype != "f32" else v,
+                           ref.view(torch.int16) if dtype != "f32" else ref), mode
+        mask = torch.ones_like(big, dtype=torch.bool)
+        mask[:, 1:R + 1, 4:C + 4] = False
+        assert torch.all(big[mask] == 3.0)
+
+
+def test_row_interleaved_3RxC_layout():
+    """Each row holds the rows of all three planes (the 3R x C layout of the
+    paper's task agglomeration); each plane keeps its own 2-pixel border."""
+    torch = _torch()
+    P, R, C = 3, 90, 300
+    host = synth.image(121, P, R, C)
+    k = synth.taps_random(122)
+    buf_in = torch.from_numpy(np.ascontiguousarray(host.transpose(1, 0, 2))).cuda()  # [R][3][C]
+    vin = buf_in.view(R, P * C).as_strided((P, R, C), (C, P * C, 1))
+    ref = gu.oracle_of(host, k)
+    for f in FORMS:
+        buf_out = torch.full((R, P * C), float("nan"), device="cuda")
+        vout = buf_out.as_strided((P, R, C), (C, P * C, 1))
+        gu.run(f, vin, k, out=vout)
+        got = buf_out.view(R, P, C).permute(1, 0, 2).cpu().numpy()
+        gu.check_f32(got, ref)
