@@ -15,6 +15,8 @@ per-plane driver of Section 5.3):
 
 ``conv5(A, k)``            single-pass (25-term) form in FP64.
 ``conv5_twopass(A, k)``    separable two-pass form in FP64.
+``conv_direct_n(A, K)``    Eq. 1 at odd width n with a full n x n kernel K.
+``conv_sep_n(A, k)``       the same with K = k k^T (products in FP64, exact).
 ``decode(bits, dtype)``    exact FP32 / FP16 / BF16 storage -> float64.
 ``round_to(x, dtype)``     float64 -> FP16 / BF16 bits, one RNE rounding.
 """
@@ -63,6 +65,8 @@ def _load():
     lib.oracle_conv5_direct.restype = None
     lib.oracle_conv5_twopass.argtypes = [dp, dp, dp, dp, i64, i64, i64]
     lib.oracle_conv5_twopass.restype = None
+    lib.oracle_conv_direct_n.argtypes = [dp, dp, dp, ctypes.c_int, i64, i64, i64, ctypes.c_int]
+    lib.oracle_conv_direct_n.restype = None
     lib.oracle_decode_f32.argtypes = [fp, dp, i64]
     lib.oracle_decode_f16.argtypes = [u16p, dp, i64]
     lib.oracle_decode_bf16.argtypes = [u16p, dp, i64]
@@ -126,6 +130,34 @@ def conv5_twopass(A, k) -> np.ndarray:
                                  _ptr(aux, ctypes.c_double), _ptr(k, ctypes.c_double),
                                  P, R, C)
     return B[0] if squeeze else B
+
+
+def conv_direct_n(A, K, nthreads: int = 1) -> np.ndarray:
+    """Eq. 1 at odd width n with a full (not necessarily separable) kernel.
+
+    K: [n, n], n odd in 1..; K[a, b] weights A[y + a - n//2, x + b - n//2].
+    Returns float64 of A's shape with the (n//2)-pixel border equal to 0.
+    """
+    squeeze = np.asarray(A).ndim == 2
+    A = _as_planes(A)
+    K = np.ascontiguousarray(np.asarray(K, dtype=np.float64))
+    if K.ndim != 2 or K.shape[0] != K.shape[1] or K.shape[0] % 2 == 0:
+        raise ValueError("K must be a square matrix of odd width")
+    B = np.empty_like(A)
+    P, R, C = A.shape
+    _load().oracle_conv_direct_n(_ptr(A, ctypes.c_double), _ptr(B, ctypes.c_double),
+                                 _ptr(K, ctypes.c_double), int(K.shape[0]), P, R, C,
+                                 int(nthreads))
+    return B[0] if squeeze else B
+
+
+def conv_sep_n(A, k, nthreads: int = 1) -> np.ndarray:
+    """Eq. 1 at odd width n with the separable kernel K = k k^T.
+
+    k holds n taps (FP32 values); their products are exact in FP64.
+    """
+    k = np.asarray(k, dtype=np.float64).reshape(-1)
+    return conv_direct_n(A, np.outer(k, k), nthreads)
 
 
 def decode(bits: np.ndarray, dtype: str) -> np.ndarray:

@@ -16,6 +16,8 @@
  *     5x5 neighbourhood lies inside the image are convolved, starting at pixel
  *     (2,2).  The paper leaves the rest untouched; this oracle fixes it to 0.
  *   - Planes are independent (Section 5.3, the per-plane driver loop).
+ *   - The same Eq. 1 at any odd width n with any n x n kernel, separable or
+ *     not (oracle_conv_direct_n), for the width-n kernels.
  *
  * All arithmetic is IEEE binary64.  The 16-bit helpers decode half and bfloat16
  * storage exactly and round binary64 results to those formats with
@@ -103,6 +105,44 @@ void oracle_conv5_twopass(const double *A, double *B, double *aux,
                     s += aux[(y + a) * cols + x] * k[a + R5];
                 Bp[y * cols + x] = s;
             }
+    }
+}
+
+/*
+ * Any odd width n = 2r+1 and any n x n kernel, separable or not: Eq. 1 with
+ * K given as a full matrix (Section 5.1 sets the n*n terms of this direct
+ * form against the 2n of the separable one).  K is row-major, K[a*n + b]
+ * weighting A[y + a - r][x + b - r] (correlation form, as above).  Border of
+ * r pixels = 0, the border rule of Section 5 applied to width n.
+ */
+void oracle_conv_direct_n(const double *A, double *B, const double *K, int n,
+                          int64_t planes, int64_t rows, int64_t cols,
+                          int nthreads)
+{
+    const int64_t plane_elems = rows * cols;
+    const int r = n / 2;
+    if (plane_elems == 0 || planes == 0)
+        return;
+    memset(B, 0, sizeof(double) * (size_t)(planes * plane_elems));
+    if (n < 1 || n % 2 == 0 || rows < n || cols < n)
+        return;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for collapse(2) schedule(static)
+#endif
+    for (int64_t p = 0; p < planes; ++p) {
+        for (int64_t y = r; y < rows - r; ++y) {
+            const double *src = A + p * plane_elems;
+            double *dst = B + p * plane_elems;
+            for (int64_t x = r; x < cols - r; ++x) {
+                double acc = 0.0;
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b)
+                        acc += src[(y + a - r) * cols + (x + b - r)] * K[a * n + b];
+                dst[y * cols + x] = acc;
+            }
+        }
     }
 }
 

@@ -211,6 +211,130 @@ def failing_pins(conv) -> list[str]:
     return bad
 
 
+# ---- pins for the width-n, full-kernel form ------------------------------
+# Each takes ``convK(A, K) -> B`` with K a full [n, n] matrix (n odd).  Kernels
+# are deliberately not symmetric, so a transposed or flipped K fails.
+
+def _interior_n(A: np.ndarray, K: np.ndarray, valid) -> np.ndarray:
+    P, R, C = A.shape
+    n = K.shape[0]
+    r = n // 2
+    B = np.zeros_like(A)
+    if R >= n and C >= n:
+        for p in range(P):
+            B[p, r:R - r, r:C - r] = valid(A[p], K)
+    return B
+
+
+def pin_n_scipy(convK) -> bool:
+    """Eq. 1 at widths 1..9 as scipy's 2-D correlation, 'valid' region."""
+    from scipy.signal import correlate2d
+
+    rng = np.random.default_rng(31)
+    for n in (1, 3, 5, 7, 9):
+        for (P, R, C) in ((2, 19, 23), (1, n, n), (3, 40, 37)):
+            A = rng.random((P, R, C)) * 2 - 1
+            K = rng.random((n, n)) * 2 - 1
+            ref = _interior_n(A, K, lambda a, K: correlate2d(a, K, mode="valid"))
+            if not np.allclose(convK(A, K), ref, rtol=0, atol=1e-13):
+                return False
+    return True
+
+
+def pin_n_torch(convK) -> bool:
+    """Eq. 1 at width 7 as torch's conv2d (cross-correlation), float64, CPU."""
+    import torch
+
+    rng = np.random.default_rng(32)
+    A = rng.random((3, 31, 26)) * 2 - 1
+    K = rng.random((7, 7)) * 2 - 1
+    valid = torch.nn.functional.conv2d(torch.from_numpy(A)[:, None],
+                                       torch.from_numpy(K)[None, None])[:, 0].numpy()
+    ref = np.zeros_like(A)
+    ref[:, 3:-3, 3:-3] = valid
+    return bool(np.allclose(convK(A, K), ref, rtol=0, atol=1e-13))
+
+
+def pin_n_bruteforce_tiny(convK) -> bool:
+    """Pure-Python Eq. 1 for n in {1, 3, 7} and every H, W in 1..10."""
+    rng = np.random.default_rng(33)
+    for n in (1, 3, 7):
+        r = n // 2
+        K = (rng.random((n, n)) * 2 - 1).tolist()
+        for R in range(1, 11):
+            for C in range(1, 11):
+                A = rng.random((1, R, C)) * 2 - 1
+                a = A[0].tolist()
+                ref = [[0.0] * C for _ in range(R)]
+                if R >= n and C >= n:
+                    for y in range(r, R - r):
+                        for x in range(r, C - r):
+                            ref[y][x] = sum(a[y + i - r][x + j - r] * K[i][j]
+                                            for i in range(n) for j in range(n))
+                if not np.allclose(convK(A, np.array(K))[0], np.array(ref), rtol=0, atol=1e-14):
+                    return False
+    return True
+
+
+def pin_n_shift(convK) -> bool:
+    """A kernel with one 1 at (a, b) moves A by (a - r, b - r): exact."""
+    rng = np.random.default_rng(34)
+    A = rng.random((1, 12, 15))
+    for n in (3, 5):
+        r = n // 2
+        for a in range(n):
+            for b in range(n):
+                K = np.zeros((n, n))
+                K[a, b] = 1.0
+                ref = np.zeros_like(A)
+                ref[0, r:12 - r, r:15 - r] = A[0, a:12 - n + 1 + a, b:15 - n + 1 + b]
+                if not np.array_equal(convK(A, K), ref):
+                    return False
+    return True
+
+
+def pin_n_delta(convK) -> bool:
+    """A unit impulse gives the kernel turned by 180 degrees around it."""
+    n, r = 9, 4
+    K = np.arange(1.0, n * n + 1).reshape(n, n)
+    A = np.zeros((1, 21, 23))
+    A[0, 10, 11] = 1.0
+    ref = np.zeros((21, 23))
+    ref[10 - r:10 + r + 1, 11 - r:11 + r + 1] = K[::-1, ::-1]
+    return bool(np.array_equal(convK(A, K)[0], ref))
+
+
+def pin_n_constant(convK) -> bool:
+    """A constant image c gives c * sum(K) on the interior, 0 on the r-border."""
+    K = np.arange(-12.0, 13.0).reshape(5, 5) / 8.0 + 0.25
+    A = np.full((2, 9, 12), 3.0)
+    ref = np.zeros_like(A)
+    ref[:, 2:-2, 2:-2] = 3.0 * K.sum()
+    return bool(np.allclose(convK(A, K), ref, rtol=1e-15, atol=0))
+
+
+CONV_N_PINS = {
+    "scipy": pin_n_scipy,
+    "torch": pin_n_torch,
+    "bruteforce_tiny": pin_n_bruteforce_tiny,
+    "shift": pin_n_shift,
+    "delta": pin_n_delta,
+    "constant": pin_n_constant,
+}
+
+
+def failing_n_pins(convK) -> list[str]:
+    bad = []
+    for name, pin in CONV_N_PINS.items():
+        try:
+            ok = pin(convK)
+        except Exception:
+            ok = False
+        if not ok:
+            bad.append(name)
+    return bad
+
+
 # ---- rounding / decoding pins -------------------------------------------
 
 def _bf16_table():

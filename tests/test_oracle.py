@@ -33,6 +33,41 @@ def test_separability_fp64():
         assert np.max(np.abs(d - t)) <= 1e-15 * 25 * scale
 
 
+@pytest.mark.parametrize("name", sorted(pins.CONV_N_PINS))
+def test_direct_n_pins(name):
+    assert pins.CONV_N_PINS[name](oracle.conv_direct_n), name
+
+
+def test_sep_n_width5_is_conv5():
+    """Width n = 5 with K = k k^T is the width-5 form, term for term."""
+    rng = np.random.default_rng(35)
+    A = rng.random((3, 23, 31))
+    k = rng.random(5) * 2 - 1
+    assert np.array_equal(oracle.conv_sep_n(A, k), oracle.conv5(A, k))
+
+
+def test_sep_n_factorises():
+    """K = k k^T: the full-kernel sum equals a row pass then a column pass
+    (written here with numpy sliding windows), to FP64 rounding."""
+    rng = np.random.default_rng(36)
+    for n in (1, 3, 7, 9):
+        r = n // 2
+        A = rng.random((2, 30, 27))
+        k = rng.random(n) * 2 - 1
+        win = np.lib.stride_tricks.sliding_window_view
+        h = (win(A, n, axis=2) * k).sum(-1)            # [P, R, C - 2r]
+        v = (win(h, n, axis=1) * k).sum(-1)            # [P, R - 2r, C - 2r]
+        ref = np.zeros_like(A)
+        ref[:, r:30 - r, r:27 - r] = v
+        got = oracle.conv_sep_n(A, k)
+        assert np.allclose(got, ref, rtol=0, atol=1e-13 * n * n)
+
+
+def test_direct_n_rejects_even_width():
+    with pytest.raises(ValueError):
+        oracle.conv_direct_n(np.zeros((1, 8, 8)), np.zeros((4, 4)))
+
+
 def _read_golden():
     cases, lines = [], [ln.strip() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
     i = 0

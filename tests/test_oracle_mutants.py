@@ -47,6 +47,29 @@ MUTANTS = [
 ]
 
 
+# Mistakes in the width-n, full-kernel function.
+N_MUTANTS = [
+    ("n_transposed_K",
+     "acc += src[(y + a - r) * cols + (x + b - r)] * K[a * n + b];",
+     "acc += src[(y + a - r) * cols + (x + b - r)] * K[b * n + a];"),
+    ("n_flipped_kernel",
+     "acc += src[(y + a - r) * cols + (x + b - r)] * K[a * n + b];",
+     "acc += src[(y - a + r) * cols + (x - b + r)] * K[a * n + b];"),
+    ("n_dropped_column",
+     "for (int b = 0; b < n; ++b)",
+     "for (int b = 0; b < n - 1; ++b)"),
+    ("n_border_off_by_one",
+     "for (int64_t x = r; x < cols - r; ++x) {",
+     "for (int64_t x = r; x < cols - r - 1; ++x) {"),
+    ("n_plane_offset_lost",
+     "const double *src = A + p * plane_elems;",
+     "const double *src = A;"),
+    ("n_radius_rounded_up",
+     "const int r = n / 2;",
+     "const int r = (n + 1) / 2;"),
+]
+
+
 def _build_mutant(tmp_path, name, old, new):
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation site for {name} must match exactly once"
@@ -116,3 +139,32 @@ def test_rounding_pins_reject_mutant(tmp_path, name, old, new):
     out = np.empty(v.shape, dtype=np.uint16)
     lib.oracle_round_f16(v.ctypes.data_as(dp), out.ctypes.data_as(u16p), v.size)
     assert not np.array_equal(out, v.astype(np.float16).view(np.uint16))
+
+
+def _wrap_n(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    f = lib.oracle_conv_direct_n
+    f.argtypes = [dp, dp, dp, ctypes.c_int, i64, i64, i64, ctypes.c_int]
+
+    def convK(A, K):
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+        K = np.ascontiguousarray(np.asarray(K, dtype=np.float64))
+        B = np.empty_like(A)
+        P, R, C = A.shape
+        p = lambda a: a.ctypes.data_as(dp)  # noqa: E731
+        f(p(A), p(B), p(K), int(K.shape[0]), P, R, C, 1)
+        return B
+
+    return convK
+
+
+@pytest.mark.parametrize("name,old,new", N_MUTANTS, ids=[m[0] for m in N_MUTANTS])
+def test_n_pins_reject_mutant(tmp_path, name, old, new):
+    lib = _build_mutant(tmp_path, name, old, new)
+    assert pins.failing_n_pins(_wrap_n(lib)), f"mutant {name} passed every pin"
+
+
+def test_n_unmutated_copy_passes(tmp_path):
+    lib = _build_mutant(tmp_path, "identity_n", "#define R5 2", "#define R5 2")
+    assert pins.failing_n_pins(_wrap_n(lib)) == []
