@@ -164,6 +164,54 @@ conv_status conv_batch_plan_launch(conv_plan *plan, hipStream_t stream);
 conv_status conv_batch_plan_destroy(conv_plan *plan);
 
 /*
+ * Any odd width n = 2r+1, 1 <= n <= CONV_MAX_WIDTH (the paper fixes n = 5;
+ * Section 5.1 weighs the O(n) work per pixel of the separable passes against
+ * the O(n^2) of the direct sum, which these entry points let a caller measure
+ * at every width).  Same image descriptor, storage types and conventions as
+ * the width-5 entry points; the frame of r pixels is written as +0.0 and an
+ * image smaller than n in either dimension comes out all zeros.
+ * Arithmetic: each 1-D filter is one multiply and n-1 fused multiply-adds in
+ * tap order; the direct form runs an n-term FMA chain per kernel row and adds
+ * the n row partials pairwise (the first half of every split is the largest
+ * power of two below its length).  At n = 5 this is exactly the arithmetic of
+ * conv_sep5_1pass / conv_sep5_2pass, and the results are bitwise equal.
+ * Returns CONV_EINVAL for an even n or n outside 1..CONV_MAX_WIDTH.
+ */
+#define CONV_MAX_WIDTH 9
+
+/*
+ * Width-n separable single pass (Eq. 1 with K = k k^T).  mode
+ * CONV_1PASS_FUSED keeps the row-filtered rows in registers; mode
+ * CONV_1PASS_DIRECT25 evaluates the n*n-term sum with K[a][b] = k[a]*k[b]
+ * rounded once to FP32 on the host.  d_out == d_in runs the single pass with
+ * copy-back, as in conv_sep5_1pass.
+ *   k   n FP32 taps (host array); k[0] weights the neighbour at offset -r.
+ */
+conv_status conv_sepn_1pass(const void *d_in, void *d_out, const float *k,
+                            int32_t n, const conv_image *img, int mode,
+                            hipStream_t stream);
+
+/*
+ * Width-n two-pass form (Section 5.1): row kernel into the FP32 workspace
+ * d_tmp (planes*rows*cols floats, or NULL for stream-ordered scratch), then
+ * column kernel into d_out.  Aliasing rules as conv_sep5_2pass.
+ */
+conv_status conv_sepn_2pass(const void *d_in, void *d_out, float *d_tmp,
+                            const float *k, int32_t n, const conv_image *img,
+                            hipStream_t stream);
+
+/*
+ * Direct width-n convolution with a full, not necessarily separable kernel
+ * (Eq. 1 as written, before the separable restriction that follows it):
+ *   B[p][y][x] = sum_{a=0..n-1} sum_{b=0..n-1} A[p][y+a-r][x+b-r] * K[a*n+b]
+ *   K   n*n FP32 weights, row-major (host array).
+ * d_out == d_in runs with copy-back.
+ */
+conv_status conv_2d_direct(const void *d_in, void *d_out, const float *K,
+                           int32_t n, const conv_image *img,
+                           hipStream_t stream);
+
+/*
  * Tile configuration (the autotuner's search space).  Results never depend on
  * it: every configuration gives bitwise identical output.
  *   rows_per_tile  output rows a wavefront walks down per tile (4..4096)

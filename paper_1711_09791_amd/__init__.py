@@ -82,6 +82,7 @@ _lib = None
 EXPORTS = (
     "conv_sep5_2pass", "conv_sep5_1pass", "conv_sep5_batch",
     "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
+    "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct",
     "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_tune",
     "conv_serve_create", "conv_serve_submit", "conv_serve_poll", "conv_serve_drain",
     "conv_serve_destroy", "conv_serve_get_stats", "conv_last_error", "conv_version",
@@ -108,6 +109,9 @@ def lib():
         "conv_sep5_batch": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, ctypes.c_int, vp],
         "conv_batch_plan_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp,
                                    ctypes.c_int, ctypes.POINTER(vp)],
+        "conv_sepn_1pass": [vp, vp, fp, i32, imgp, ctypes.c_int, vp],
+        "conv_sepn_2pass": [vp, vp, vp, fp, i32, imgp, vp],
+        "conv_2d_direct": [vp, vp, fp, i32, imgp, vp],
         "conv_batch_plan_launch": [vp, vp],
         "conv_batch_plan_destroy": [vp],
         "conv_get_tile_cfg": [i32, i32, cfgp],
@@ -223,6 +227,22 @@ def _taps(k) -> ctypes.Array:
     return (ctypes.c_float * 5)(*vals)
 
 
+def _taps_n(k) -> tuple[ctypes.Array, int]:
+    """Any number of FP32 taps (the library checks the width)."""
+    vals = [float(v) for v in (k.reshape(-1).tolist() if hasattr(k, "reshape") else k)]
+    return (ctypes.c_float * max(len(vals), 1))(*vals), len(vals)
+
+
+def _kernel_nn(K) -> tuple[ctypes.Array, int]:
+    """A square n x n kernel (nested sequence, array or tensor) -> row-major FP32."""
+    rows = K.tolist() if hasattr(K, "tolist") else [list(r) for r in K]
+    n = len(rows)
+    if any(len(r) != n for r in rows):
+        raise ValueError("K must be a square n x n kernel")
+    vals = [float(v) for r in rows for v in r]
+    return (ctypes.c_float * max(len(vals), 1))(*vals), n
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -260,6 +280,37 @@ def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
         img = image_of(d_in)
     return _check(lib().conv_sep5_1pass(_ptr(d_in), _ptr(d_out), _taps(k), ctypes.byref(img),
                                         int(mode), _stream(stream)))
+
+
+def conv_sepn_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
+                    img: conv_image | None = None, stream=None):
+    """Width-n separable single pass, n = len(k) odd in 1..9 (fused or direct)."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    taps, n = _taps_n(k)
+    return _check(lib().conv_sepn_1pass(_ptr(d_in), _ptr(d_out), taps, n, ctypes.byref(img),
+                                        int(mode), _stream(stream)))
+
+
+def conv_sepn_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, stream=None):
+    """Width-n two-pass form, n = len(k) odd in 1..9."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    taps, n = _taps_n(k)
+    return _check(lib().conv_sepn_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), taps, n,
+                                        ctypes.byref(img), _stream(stream)))
+
+
+def conv_2d_direct(d_in, d_out, K, img: conv_image | None = None, stream=None):
+    """Direct convolution with a full n x n kernel K (n odd in 1..9)."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    w, n = _kernel_nn(K)
+    return _check(lib().conv_2d_direct(_ptr(d_in), _ptr(d_out), w, n, ctypes.byref(img),
+                                       _stream(stream)))
 
 
 def _batch_args(ins, outs, ks, imgs):

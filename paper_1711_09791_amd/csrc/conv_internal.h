@@ -54,6 +54,16 @@ struct BatchArgs {
     int64_t total;
 };
 
+// Taps of the width-n kernels (n = 2R+1 <= 9).
+struct TapsN {
+    float k[9];    // separable taps k[0..n)
+    float K[81];   // n x n kernel, row-major: K[a*n + b] weights A[y+a-R][x+b-R]
+};
+constexpr int kMaxWidthN = 9;
+constexpr int kThSepN = 8;     // rows per band: fused, row and column kernels
+constexpr int kThDirectN = 4;  // rows per band: direct n x n
+constexpr int waves_n(int dtype) { return dtype == 0 ? 2 : 1; }
+
 // Elements per lane per row: 16 bytes of storage.
 inline int vec_of(int dtype) { return dtype == 0 ? 4 : 8; }
 inline int esize_of(int dtype) { return dtype == 0 ? 4 : 2; }
@@ -76,6 +86,20 @@ hipError_t launch_batch_args_f16(const BatchArgs &a, int mode, int waves, int th
                                  hipStream_t s);
 hipError_t launch_batch_args_bf16(const BatchArgs &a, int mode, int waves, int th, int grid,
                                   hipStream_t s);
+
+hipError_t launch_image_n_f32(const ImgDev &im, const TapsN &tp, int radius, int mode,
+                             int64_t nblocks, hipStream_t s);
+hipError_t launch_image_n_f16(const ImgDev &im, const TapsN &tp, int radius, int mode,
+                             int64_t nblocks, hipStream_t s);
+hipError_t launch_image_n_bf16(const ImgDev &im, const TapsN &tp, int radius, int mode,
+                              int64_t nblocks, hipStream_t s);
+
+inline hipError_t launch_image_n(const ImgDev &im, const TapsN &tp, int dtype, int radius, int mode,
+                                 int64_t nblocks, hipStream_t s) {
+    return dtype == 0 ? launch_image_n_f32(im, tp, radius, mode, nblocks, s)
+         : dtype == 1 ? launch_image_n_f16(im, tp, radius, mode, nblocks, s)
+                      : launch_image_n_bf16(im, tp, radius, mode, nblocks, s);
+}
 
 inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
                                hipStream_t s) {

@@ -1,0 +1,348 @@
+// conv_kernels_n.h -- Eq. 1 of arXiv 1711.09791 for any odd width n = 2R+1,
+// R = 0..4: the separable forms (fused single pass, two-pass row and column
+// kernels, direct n*n with K = k k^T) and the direct form with a general,
+// non-separable n x n kernel K.  The O(n) separable passes against the O(n^2)
+// direct sum are the trade-off of Section 5.1.
+//
+// Same machinery as the width-5 kernels (conv_kernels.h): a wave64 tile of
+// 64*VEC columns x a band of TH rows, strip-fastest launch order, one 16-byte
+// buffer load per lane per row, R-column halos from neighbouring lanes by DPP,
+// per-row buffer resources so that lanes past the edge read 0 and drop their
+// stores.  Every band is fully unrolled: all TH+2R input rows are issued
+// first; a short last band computes TH rows and stores only its own.  The
+// output frame of R pixels is written as +0.0.
+//
+// Arithmetic (fixed for every tile shape):
+//   horizontal  h = v[x-R]*k0; h = fma(v[x-R+1], k1, h); ... (n taps)
+//   vertical    o = h[y-R]*k0; o = fma(h[y-R+1], k1, o); ...
+//   direct      p_a = the same n-term chain over kernel row a with K[a][.],
+//               then a pairwise sum of the n row partials: the first half is
+//               the largest power of two below n, recursively.
+// For n = 5 this is exactly the arithmetic of the width-5 kernels.
+#pragma once
+
+#include "conv_kernels.h"
+
+namespace convsep5 {
+namespace {
+
+// ---- rows with R-column halos ---------------------------------------------------
+template <class D, bool AL, int R> struct RawN;
+template <class D, int R> struct RawN<D, true, R> {
+    static constexpr int HW = (R * D::ESZ + 3) / 4;  // halo words on each side
+    u4 m;
+    uint32_t h[HW > 0 ? HW : 1];
+};
+template <class D, int R> struct RawN<D, false, R> { uint32_t e[D::VEC + 2 * R]; };
+
+template <int HW>
+__device__ __forceinline__ void load_words(uint32_t (&h)[HW > 0 ? HW : 1],
+                                           __amdgpu_buffer_rsrc_t rs, int off) {
+    if constexpr (HW == 1) {
+        h[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    } else if constexpr (HW == 2) {
+        const u2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        h[0] = q.x;
+        h[1] = q.y;
+    } else if constexpr (HW == 3) {
+        typedef uint32_t u3 __attribute__((ext_vector_type(3)));
+        const u3 q = __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0);
+        h[0] = q.x;
+        h[1] = q.y;
+        h[2] = q.z;
+    } else if constexpr (HW == 4) {
+        const u4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        h[0] = q.x;
+        h[1] = q.y;
+        h[2] = q.z;
+        h[3] = q.w;
+    }
+}
+
+// Byte offset of the halo load: lane 0 loads the HW words left of the strip,
+// lane 63 the HW words right of it; other lanes (and halos outside the row)
+// get an out-of-range offset.
+template <class D, int R>
+__device__ __forceinline__ int halo_offset_n(int xs, int W, int lane) {
+    constexpr int HW = (R * D::ESZ + 3) / 4;
+    constexpr int HE = HW * 4 / D::ESZ;  // halo elements covered by HW words
+    if constexpr (HW == 0) {
+        return OOB;
+    } else {
+        const int hl = xs - HE, hr = xs + WAVE * D::VEC;
+        return lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
+                         : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
+    }
+}
+
+template <class D, int R>
+__device__ __forceinline__ void issue_n(RawN<D, true, R> &r, const char *row, uint32_t rbytes,
+                                        int x, int hoff) {
+    const auto rs = row_rsrc(row, rbytes);
+    r.m = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, 0);
+    load_words<RawN<D, true, R>::HW>(r.h, rs, hoff);
+}
+template <class D, int R>
+__device__ __forceinline__ void issue_n(RawN<D, false, R> &r, const char *row, uint32_t rbytes,
+                                        int x, int) {
+    const auto rs = row_rsrc(row, rbytes);
+#pragma unroll
+    for (int e = 0; e < D::VEC + 2 * R; ++e) {
+        const int c = x - R + e;
+        const int off = c >= 0 ? c * D::ESZ : OOB;
+        if constexpr (D::ESZ == 4)
+            r.e[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        else
+            r.e[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+    }
+}
+
+// v[i] = A[x - R + i], i = 0 .. VEC+2R-1, as FP32.
+template <class D, int R>
+__device__ __forceinline__ void decode_n(const RawN<D, true, R> &r, float (&v)[D::VEC + 2 * R]) {
+    constexpr int HW = RawN<D, true, R>::HW;
+    const uint32_t m[4] = {r.m.x, r.m.y, r.m.z, r.m.w};
+    // words of the lane's extended row: HW from the left lane, its own 4, HW
+    // from the right lane (lane 0 / 63 keep their own halo words instead)
+    uint32_t ext[4 + 2 * HW];
+#pragma unroll
+    for (int j = 0; j < HW; ++j) ext[j] = from_left(m[4 - HW + j], r.h[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) ext[HW + j] = m[j];
+#pragma unroll
+    for (int j = 0; j < HW; ++j) ext[HW + 4 + j] = from_right(m[j], r.h[j]);
+    if constexpr (D::ESZ == 4) {
+#pragma unroll
+        for (int i = 0; i < D::VEC + 2 * R; ++i) v[i] = __uint_as_float(ext[i]);
+    } else {
+        constexpr int SH = 2 * HW - R;  // halves of ext before A[x - R]
+#pragma unroll
+        for (int i = 0; i < D::VEC + 2 * R; ++i) {
+            const int j = i + SH;
+            v[i] = dec(D{}, (j & 1) ? (ext[j >> 1] >> 16) : ext[j >> 1]);
+        }
+    }
+}
+template <class D, int R>
+__device__ __forceinline__ void decode_n(const RawN<D, false, R> &r, float (&v)[D::VEC + 2 * R]) {
+#pragma unroll
+    for (int e = 0; e < D::VEC + 2 * R; ++e) v[e] = dec(D{}, r.e[e]);
+}
+
+// ---- the arithmetic ---------------------------------------------------------------
+
+template <int N, int R>
+__device__ __forceinline__ void hfilter_n(const float (&v)[N + 2 * R], const float *k, float (&h)[N]) {
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+        float t = v[e] * k[0];
+#pragma unroll
+        for (int b = 1; b <= 2 * R; ++b) t = __builtin_fmaf(v[e + b], k[b], t);
+        h[e] = t;
+    }
+}
+
+// Pairwise sum of p[LO..HI): split at the largest power of two below HI-LO.
+template <int LO, int HI, int M>
+__device__ __forceinline__ float pairwise(const float (&p)[M]) {
+    if constexpr (HI - LO == 1) {
+        return p[LO];
+    } else {
+        constexpr int n = HI - LO;
+        constexpr int half = n >= 8 ? (n > 8 ? 8 : 4) : (n > 4 ? 4 : (n > 2 ? 2 : 1));
+        return pairwise<LO, LO + half, M>(p) + pairwise<LO + half, HI, M>(p);
+    }
+}
+
+// ---- one band ---------------------------------------------------------------------
+// MODE: MODE_FUSED (separable, register window), MODE_DIRECT25 (direct n x n
+// with tp.K), MODE_ROWPASS / MODE_COLPASS (two-pass kernels).
+template <class D, bool AL, int R, int MODE, bool EDGE, int TH>
+__device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int plane, int xs, int y0,
+                                       int y1, int lane) {
+    constexpr int VEC = D::VEC;
+    constexpr int NT_ = 2 * R + 1;
+    const int H = im.rows, W = im.cols;
+    const int x = xs + lane * VEC;
+    bool cm[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= R) && (x + e < W - R);
+
+    if constexpr (MODE == MODE_ROWPASS) {
+        const char *sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+        const int64_t sstride = im.pitch * D::ESZ;
+        char *tbase = (char *)(im.tmp + (int64_t)plane * H * W);
+        const int hoff = halo_offset_n<D, R>(xs, W, lane);
+        RawN<D, AL, R> raw[TH];
+#pragma unroll
+        for (int i = 0; i < TH; ++i)
+            issue_n<D, R>(raw[i], sbase + (int64_t)min(y0 + i, y1 - 1) * sstride,
+                          (uint32_t)W * D::ESZ, x, hoff);
+#pragma unroll
+        for (int i = 0; i < TH; ++i) {
+            float v[VEC + 2 * R], h[VEC];
+            decode_n<D, R>(raw[i], v);
+            hfilter_n<VEC, R>(v, tp.k, h);
+            if constexpr (EDGE) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) h[e] = cm[e] ? h[e] : 0.0f;
+            }
+            if (y0 + i < y1)
+                store_t<VEC, AL>(tbase + (int64_t)(y0 + i) * W * 4, (uint32_t)W * 4, x, h);
+        }
+        return;
+    } else {
+        constexpr bool COL = MODE == MODE_COLPASS;
+        constexpr bool DIRECT = MODE == MODE_DIRECT25;
+        constexpr int WN = DIRECT ? VEC + 2 * R : VEC;
+        using RawIn = typename std::conditional<COL, RawT<VEC, AL>, RawN<D, AL, R>>::type;
+        const char *sbase;
+        int64_t sstride;
+        uint32_t sbytes;
+        if constexpr (COL) {
+            sbase = (const char *)(im.tmp + (int64_t)plane * H * W);
+            sstride = (int64_t)W * 4;
+            sbytes = (uint32_t)W * 4;
+        } else {
+            sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+            sstride = im.pitch * D::ESZ;
+            sbytes = (uint32_t)W * D::ESZ;
+        }
+        char *dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
+        const int64_t dstride = im.pitch * D::ESZ;
+        const int hoff = halo_offset_n<D, R>(xs, W, lane);
+        RawIn raw[TH + 2 * R];
+#pragma unroll
+        for (int i = 0; i < TH + 2 * R; ++i) {
+            const char *p = sbase + (int64_t)clampi(y0 - R + i, 0, H - 1) * sstride;
+            if constexpr (COL)
+                issue_t<VEC, AL>(raw[i], p, sbytes, x);
+            else
+                issue_n<D, R>(raw[i], p, sbytes, x, hoff);
+        }
+        float w[TH + 2 * R][WN];
+#pragma unroll
+        for (int i = 0; i < TH + 2 * R; ++i) {
+            if constexpr (COL) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) w[i][e] = __uint_as_float(raw[i].w[e]);
+            } else if constexpr (DIRECT) {
+                decode_n<D, R>(raw[i], w[i]);
+            } else {
+                float v[VEC + 2 * R];
+                decode_n<D, R>(raw[i], v);
+                hfilter_n<VEC, R>(v, tp.k, w[i]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < TH; ++j) {
+            const int y = y0 + j;
+            if (y >= y1) break;
+            float o[VEC];
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (DIRECT) {
+                    float p[NT_];
+#pragma unroll
+                    for (int a = 0; a < NT_; ++a) {
+                        float t = w[j + a][e] * tp.K[a * NT_];
+#pragma unroll
+                        for (int b = 1; b < NT_; ++b)
+                            t = __builtin_fmaf(w[j + a][e + b], tp.K[a * NT_ + b], t);
+                        p[a] = t;
+                    }
+                    o[e] = pairwise<0, NT_, NT_>(p);
+                } else {
+                    float t = w[j][e] * tp.k[0];
+#pragma unroll
+                    for (int a = 1; a < NT_; ++a) t = __builtin_fmaf(w[j + a][e], tp.k[a], t);
+                    o[e] = t;
+                }
+            }
+            if constexpr (EDGE) {
+                const bool vr = (y >= R) && (y < H - R);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) o[e] = (vr && cm[e]) ? o[e] : 0.0f;
+            }
+            store_out<D, AL>(dbase + (int64_t)y * dstride, (uint32_t)W * D::ESZ, x, o);
+        }
+    }
+}
+
+template <class D, bool AL, int R, int MODE, int WAVES, int TH>
+__device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, int64_t lt, int wave,
+                                           int lane) {
+    const int sg = (int)(lt % im.nsg);
+    const int64_t t = lt / im.nsg;
+    const int band = (int)(t % im.nb);
+    const int plane = (int)(t / im.nb);
+    const int strip = sg * WAVES + wave;
+    if (strip >= im.ns) return;
+    const int xs = strip * (WAVE * D::VEC);
+    const int y0 = band * TH;
+    const int y1 = min(y0 + TH, im.rows);
+    const bool col_edge = xs < R || xs + WAVE * D::VEC > im.cols - R;
+    const bool row_edge = MODE != MODE_ROWPASS && (y0 < R || y0 + TH > im.rows - R);
+    if (col_edge || row_edge)
+        band_n<D, AL, R, MODE, true, TH>(im, tp, plane, xs, y0, y1, lane);
+    else
+        band_n<D, AL, R, MODE, false, TH>(im, tp, plane, xs, y0, y1, lane);
+}
+
+template <class D, bool AL, int R, int MODE, int WAVES, int TH>
+__global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, int64_t nblocks) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    for (int64_t lt = blockIdx.x; lt < nblocks; lt += gridDim.x)
+        run_tile_n<D, AL, R, MODE, WAVES, TH>(im, tp, lt, wave, lane);
+}
+
+// Band heights and workgroup widths of the width-n kernels (shared with the
+// host, which builds the tile geometry).
+template <class D> struct GeomN {
+    static constexpr int WAVES = waves_n(D::ESZ == 4 ? 0 : 1);
+    static constexpr int TH_SEP = kThSepN;
+    static constexpr int TH_DIRECT = kThDirectN;
+};
+
+template <class D, bool AL, int R, int MODE>
+hipError_t launch_n_m(const ImgDev &im, const TapsN &tp, int64_t nblocks, hipStream_t s) {
+    constexpr int W = GeomN<D>::WAVES;
+    constexpr int TH = MODE == MODE_DIRECT25 ? GeomN<D>::TH_DIRECT : GeomN<D>::TH_SEP;
+    const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
+    hipLaunchKernelGGL((k_image_n<D, AL, R, MODE, W, TH>), dim3(grid), dim3(WAVE * W), 0, s, im, tp,
+                       nblocks);
+    return hipGetLastError();
+}
+
+template <class D, bool AL, int R>
+hipError_t launch_n_r(const ImgDev &im, const TapsN &tp, int mode, int64_t nblocks, hipStream_t s) {
+    switch (mode) {
+    case MODE_FUSED: return launch_n_m<D, AL, R, MODE_FUSED>(im, tp, nblocks, s);
+    case MODE_DIRECT25: return launch_n_m<D, AL, R, MODE_DIRECT25>(im, tp, nblocks, s);
+    case MODE_ROWPASS: return launch_n_m<D, AL, R, MODE_ROWPASS>(im, tp, nblocks, s);
+    default: return launch_n_m<D, AL, R, MODE_COLPASS>(im, tp, nblocks, s);
+    }
+}
+
+template <class D, bool AL>
+hipError_t launch_n_a(const ImgDev &im, const TapsN &tp, int radius, int mode, int64_t nblocks,
+                      hipStream_t s) {
+    switch (radius) {
+    case 0: return launch_n_r<D, AL, 0>(im, tp, mode, nblocks, s);
+    case 1: return launch_n_r<D, AL, 1>(im, tp, mode, nblocks, s);
+    case 2: return launch_n_r<D, AL, 2>(im, tp, mode, nblocks, s);
+    case 3: return launch_n_r<D, AL, 3>(im, tp, mode, nblocks, s);
+    default: return launch_n_r<D, AL, 4>(im, tp, mode, nblocks, s);
+    }
+}
+
+template <class D>
+hipError_t launch_image_n_t(const ImgDev &im, const TapsN &tp, int radius, int mode,
+                            int64_t nblocks, hipStream_t s) {
+    return im.aligned ? launch_n_a<D, true>(im, tp, radius, mode, nblocks, s)
+                      : launch_n_a<D, false>(im, tp, radius, mode, nblocks, s);
+}
+
+}  // namespace
+}  // namespace convsep5

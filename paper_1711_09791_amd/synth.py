@@ -58,6 +58,28 @@ def taps_signed(seed: int) -> np.ndarray:
     return (rng.random(5) * 2.0 - 1.0).astype(np.float32)
 
 
+def taps_binomial_n(n: int) -> np.ndarray:
+    """Binomial row n-1 over 2^(n-1) as FP32 (exact for n <= 25)."""
+    from math import comb
+
+    return (np.array([comb(n - 1, i) for i in range(n)], dtype=np.float64)
+            / 2.0 ** (n - 1)).astype(np.float32)
+
+
+def taps_random_n(seed: int, n: int) -> np.ndarray:
+    """n positive taps normalised to sum 1 in FP64, then rounded to FP32."""
+    rng = np.random.default_rng(seed)
+    raw = rng.random(n) + 1e-3
+    return (raw / raw.sum()).astype(np.float32)
+
+
+def kernel_signed(seed: int, n: int) -> np.ndarray:
+    """A full n x n FP32 kernel with signed entries uniform in [-1, 1) (not
+    separable: rank n with probability 1)."""
+    rng = np.random.default_rng(seed)
+    return (rng.random((n, n)) * 2.0 - 1.0).astype(np.float32)
+
+
 def batch_shapes(seed: int, n: int) -> list[tuple[int, int]]:
     """n (rows, cols) pairs, each 8 * U{30..270} (240..2160, multiples of 8)."""
     rng = np.random.default_rng(seed)

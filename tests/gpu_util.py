@@ -74,6 +74,32 @@ def check_f32(got: np.ndarray, ref: np.ndarray, tol: float = 1e-6) -> float:
     return e
 
 
+def gate16(got_bits: np.ndarray, ref: np.ndarray, dtype: str, margin_u: float = 12):
+    """16-bit storage gate: the output equals the oracle's exact result rounded
+    once to `dtype` (RNE), or is the neighbouring value where the exact result
+    lies within the FP32 path's error bound (margin_u * u * |r|) of the
+    rounding midpoint.  Returns (max relative error vs the unrounded oracle,
+    count of midpoint cases)."""
+    ref_bits = oracle.round_to(ref, dtype)
+    bad = got_bits != ref_bits
+    n_mid = 0
+    if np.any(bad):
+        g = got_bits[bad].astype(np.int64)
+        rb = ref_bits[bad].astype(np.int64)
+        assert np.all(np.abs(g - rb) == 1), "output differs by more than one unit"
+        gv = oracle.decode(got_bits[bad], dtype)
+        rv = oracle.decode(ref_bits[bad], dtype)
+        mid = (gv + rv) / 2
+        r = ref[bad]
+        assert np.all(np.abs(r - mid) <= margin_u * U32 * np.abs(r)), "not a midpoint case"
+        n_mid = int(bad.sum())
+    got = oracle.decode(got_bits, dtype)
+    z = ref == 0
+    assert np.all(got[z] == 0)
+    e = float(np.max(np.abs(got[~z] - ref[~z]) / np.abs(ref[~z]))) if np.any(~z) else 0.0
+    return e, n_mid
+
+
 def border_is_zero(got: np.ndarray) -> bool:
     P, R, C = got.shape
     m = np.ones((R, C), bool)

@@ -214,3 +214,37 @@ def test_row_interleaved_planes_accepted():
     i = img(planes=3, rows=16, cols=16, pitch=48, plane_stride=16)
     assert call1(i, b=0) == cs.CONV_EINVAL
     assert "NULL" in cs.conv_last_error()
+
+
+K9 = (ctypes.c_float * 81)(*([1.0] * 81))
+
+
+def test_width_n_validation():
+    L = cs.lib()
+    i = img()
+    for n in (0, 2, 4, 10, 11, -1):
+        assert L.conv_sepn_1pass(A, B, K9, n, ctypes.byref(i), 0, None) == cs.CONV_EINVAL
+        assert L.conv_sepn_2pass(A, B, None, K9, n, ctypes.byref(i), None) == cs.CONV_EINVAL
+        assert L.conv_2d_direct(A, B, K9, n, ctypes.byref(i), None) == cs.CONV_EINVAL
+        assert "width" in cs.conv_last_error()
+    assert L.conv_sepn_1pass(A, B, K9, 3, ctypes.byref(i), 2, None) == cs.CONV_EINVAL
+    assert L.conv_sepn_1pass(A, B, None, 3, ctypes.byref(i), 0, None) == cs.CONV_EINVAL
+    assert L.conv_2d_direct(A, B, None, 3, ctypes.byref(i), None) == cs.CONV_EINVAL
+    assert L.conv_2d_direct(0, B, K9, 3, ctypes.byref(i), None) == cs.CONV_EINVAL
+    assert L.conv_sepn_1pass(A, A + 4, K9, 7, ctypes.byref(i), 0, None) == cs.CONV_EALIAS
+    assert L.conv_2d_direct(A, A + 4, K9, 9, ctypes.byref(i), None) == cs.CONV_EALIAS
+    assert L.conv_sepn_2pass(A, B, A + 8, K9, 5, ctypes.byref(i), None) == cs.CONV_EALIAS
+    bad = img(pitch=3)
+    assert L.conv_2d_direct(A, B, K9, 3, ctypes.byref(bad), None) == cs.CONV_EINVAL
+    for e in (img(planes=0), img(rows=0), img(cols=0)):
+        for n in (1, 3, 9):
+            assert L.conv_sepn_1pass(0, 0, K9, n, ctypes.byref(e), 1, None) == cs.CONV_OK
+            assert L.conv_sepn_2pass(0, 0, None, K9, n, ctypes.byref(e), None) == cs.CONV_OK
+            assert L.conv_2d_direct(0, 0, K9, n, ctypes.byref(e), None) == cs.CONV_OK
+
+
+def test_width_n_binding_rejects_non_square_kernel():
+    with pytest.raises(ValueError):
+        cs._kernel_nn([[1.0, 2.0, 3.0], [4.0, 5.0]])
+    taps, n = cs._kernel_nn([[1.0] * 3] * 3)
+    assert n == 3 and len(taps) == 9

@@ -22,25 +22,7 @@ FORMS = ("2pass", "fused", "direct")
 
 def gate(got_bits: np.ndarray, ref: np.ndarray, dtype: str):
     """Returns (max relative error vs unrounded oracle, count of midpoint cases)."""
-    ref_bits = oracle.round_to(ref, dtype)
-    ok = got_bits == ref_bits
-    bad = ~ok
-    n_mid = 0
-    if np.any(bad):
-        g = got_bits[bad].astype(np.int64)
-        rb = ref_bits[bad].astype(np.int64)
-        assert np.all(np.abs(g - rb) == 1), "output differs by more than one unit"
-        gv = oracle.decode(got_bits[bad], dtype)
-        rv = oracle.decode(ref_bits[bad], dtype)
-        mid = (gv + rv) / 2
-        r = ref[bad]
-        assert np.all(np.abs(r - mid) <= 12 * gu.U32 * np.abs(r)), "not a midpoint case"
-        n_mid = int(bad.sum())
-    got = oracle.decode(got_bits, dtype)
-    z = ref == 0
-    assert np.all(got[z] == 0)
-    e = float(np.max(np.abs(got[~z] - ref[~z]) / np.abs(ref[~z]))) if np.any(~z) else 0.0
-    return e, n_mid
+    return gu.gate16(got_bits, ref, dtype, margin_u=12)
 
 
 LIMIT = {"f16": 2e-3, "bf16": 2.0 ** -8}
