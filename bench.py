@@ -18,6 +18,10 @@ Also measured and reported in the same JSON line:
              own taps: p50/p99 latency of the continuous-batching server
              against the same server restricted to one image per launch, at
              0.5x and 0.8x of the batched server's measured capacity;
+  widths     odd widths n = 1..9 on the same image: fused, two-pass and
+             direct (n*n terms) separable forms and a full non-separable
+             n x n kernel, each against the HBM and the FP32 ALU roofline
+             (the O(n) vs O(n^2) trade-off of Section 5.1);
   cpu_baseline  the FP64 oracle on the host cores, on the whole image.
 
 Prints ONE JSON line.  Run with no flags for the default configuration.
@@ -38,6 +42,9 @@ if ROOT not in sys.path:
 
 P, R, C = 3, 4096, 4096
 HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA rate without packed FP32 math (the kernels are built with
+# packed FP32 off): 256 CUs x 64 lanes x 2 flop x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_DIR = os.path.join(ROOT, "paper_1711_09791_amd", "csrc")
 
@@ -46,12 +53,16 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # After an idle moment the GPU's clocks dip and recover over ~600 launches
+    # (~25 ms) of this kernel; 1000 warm-up launches reach the steady state.
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--sets", type=int, default=3, help="rotating buffer sets")
     ap.add_argument("--forms", default="fused,2pass,direct25,copy,1pass_copyback,2pass_inplace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision, batch and serving measurements")
+                    help="skip the precision, widths, batch and serving measurements")
+    ap.add_argument("--extras", default="precision,widths,batch,serving",
+                    help="comma list of extra measurements to run")
     ap.add_argument("--warm", action="store_true",
                     help="also time the fused form on one buffer set (cache-warm)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -102,6 +113,14 @@ def timed(torch, fn, steps, warmup):
     t1.record()
     torch.cuda.synchronize()
     return t0.elapsed_time(t1)
+
+
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One line on stderr per finished measurement (the JSON line is stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def check(cs, st):
@@ -172,6 +191,53 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
     return res, eq
 
 
+def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
+    """Width-n forms on the 3x4096x4096 FP32 image: time per launch, MPix/s and
+    both rooflines.  flops per plane-pixel: an n-tap filter is 1 multiply and
+    n-1 FMAs (2n-1 flops); fused / two-pass run two of them, the direct forms n
+    row chains plus n-1 adds (2n^2-1)."""
+    dev = torch.device("cuda:0")
+    base = torch.from_numpy(host).to(dev)
+    S = max(1, args.sets)
+    ins = [base] + [base.clone() for _ in range(S - 1)]
+    outs = [torch.empty_like(base) for _ in range(S)]
+    tmp = torch.empty(P * R * C, device=dev)
+    L = cs.lib()
+    img = cs.image_of(base)
+    pimg = ctypes.byref(img)
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+    pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
+    ptmp = ctypes.c_void_p(tmp.data_ptr())
+    steps = max(10, min(args.steps, 100))
+    res = {}
+    for n in widths:
+        k = synth.taps_random_n(2 + n, n)
+        K = synth.kernel_signed(3 + n, n)
+        kk = (ctypes.c_float * n)(*[float(v) for v in k])
+        KK = (ctypes.c_float * (n * n))(*[float(v) for v in K.reshape(-1)])
+        fns = {
+            "fused": lambda i: check(cs, L.conv_sepn_1pass(pin[i % S], pout[i % S], kk, n, pimg, 0, hs)),
+            "2pass": lambda i: check(cs, L.conv_sepn_2pass(pin[i % S], pout[i % S], ptmp, kk, n, pimg, hs)),
+            "direct": lambda i: check(cs, L.conv_sepn_1pass(pin[i % S], pout[i % S], kk, n, pimg, 1, hs)),
+            "full": lambda i: check(cs, L.conv_2d_direct(pin[i % S], pout[i % S], KK, n, pimg, hs)),
+        }
+        row = {}
+        for name, fn in fns.items():
+            avg = timed(torch, fn, steps, max(3, args.warmup // 2)) / steps
+            nbytes = (16 if name == "2pass" else 8) * P * R * C
+            flops = ((4 * n - 2) if name in ("fused", "2pass") else (2 * n * n - 1)) * P * R * C
+            row[name] = {
+                "ms_per_step": avg,
+                "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
+                "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "frac_of_alu_peak": flops / (avg * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+            }
+        res[f"n{n}"] = row
+    del ins, outs, tmp
+    return {"alu_peak_tflops": ALU_PEAK_TFLOPS, "steps": steps, "results": res}
+
+
 def bench_batch(torch, cs, synth, args):
     """64 uneven FP32 images: persistent batch launch, graph replay, per-image launches."""
     shapes = synth.batch_shapes(3, 64)
@@ -180,13 +246,29 @@ def bench_batch(torch, cs, synth, args):
     ks = [synth.taps_random(200 + i) for i in range(64)]
     pix = sum(h * w for h, w in shapes)
     nbytes = 24 * pix
-    steps = max(10, args.steps // 10)
-    t_eager = timed(torch, lambda i: cs.conv_sep5_batch(ins, outs, ks), steps, 3)
+    steps = max(20, args.steps // 4)
+    warm = max(3, args.warmup // 10)
+    # arguments marshalled once, so that the timed loops measure the launches
+    L = cs.lib()
+    n = len(ins)
+    pin = (ctypes.c_void_p * n)(*[a.data_ptr() for a in ins])
+    pout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    kk = (ctypes.c_float * (5 * n))(*[float(v) for k in ks for v in k])
+    imgs = (cs.conv_image * n)(*[cs.image_of(a) for a in ins])
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    t_eager = timed(torch, lambda i: check(cs, L.conv_sep5_batch(n, pin, pout, kk, imgs, 0, hs)),
+                    steps, warm)
     plan = cs.conv_batch_plan_create(ins, outs, ks)
-    t_graph = timed(torch, lambda i: plan.launch(), steps, 3)
+    t_graph = timed(torch, lambda i: plan.launch(), steps, warm)
     plan.destroy()
-    t_lone = timed(torch, lambda i: [cs.conv_sep5_1pass(a, o, k) for a, o, k in zip(ins, outs, ks)],
-                   steps, 3)
+    one = [(ctypes.c_void_p(pin[j]), ctypes.c_void_p(pout[j]), (ctypes.c_float * 5)(*kk[5 * j:5 * j + 5]),
+            ctypes.byref(imgs[j])) for j in range(n)]
+
+    def lone(i):
+        for a, o, k, im in one:
+            check(cs, L.conv_sep5_1pass(a, o, k, im, 0, hs))
+
+    t_lone = timed(torch, lone, steps, warm)
     cfg = cs.conv_get_tile_cfg(0, 1).as_dict()
     ms_e, ms_g, ms_l = t_eager / steps, t_graph / steps, t_lone / steps
     return {
@@ -340,17 +422,28 @@ def main():
     k = synth.taps_random(2)
     forms_list = [f for f in args.forms.split(",") if f]
     forms, eq = bench_image(torch, cs, host, k, args, forms=forms_list)
+    progress("forms: " + ", ".join(f"{n} {v['avg_launch_ms'] * 1e3:.1f} us" for n, v in forms.items()))
 
     extras = {}
-    if not args.no_extras:
+    want = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    if "precision" in want:
         prec = {}
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
             r, _ = bench_image(torch, cs, host, k, args, dtype=dt, forms=("fused", "direct25"))
             prec[name] = r
         extras["precision"] = prec
+        progress("precision done")
+    if "widths" in want:
+        extras["widths"] = bench_widths(torch, cs, synth, host, args)
+        progress("widths done")
+    if "batch" in want:
         extras["batch"] = bench_batch(torch, cs, synth, args)
+        progress("batch done")
+    if "serving" in want:
         extras["serving"] = bench_serving(torch, cs, synth, args)
+        progress("serving (mixed frames) done")
         extras["serving_small_frames"] = bench_serving(torch, cs, synth, args, sizes=[(480, 640)])
+        progress("serving (small frames) done")
 
     main_form = "fused"
     f = forms[main_form]
@@ -369,6 +462,7 @@ def main():
         import oracle
 
         cpu = cpu_baseline(oracle, np, host, k, args)
+        progress("cpu baseline done")
 
     line = {
         "metric": "MPix/s (3-plane) + % HBM roofline; serving p50/p99 latency vs per-image launch",

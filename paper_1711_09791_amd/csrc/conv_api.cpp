@@ -90,12 +90,13 @@ bool overlaps(const void *a, int64_t na, const void *b, int64_t nb) {
 
 // ---- tile configuration ---------------------------------------------------------
 static std::mutex g_cfg_mu;
-// Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image; the
-// 64-image uneven batch); conv_tune re-derives them for a given workload.
+// Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image: 8-row
+// bands, one wave per workgroup, XCDs taking turns on chunks of 8 band rows;
+// the 64-image uneven batch); conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][2] = {
-    {{8, 2, 0, 0}, {16, 1, 8, 0}},
-    {{32, 4, 0, 0}, {16, 1, 8, 0}},
-    {{32, 4, 0, 0}, {16, 1, 8, 0}},
+    {{8, 1, 0, 8}, {16, 1, 8, 0}},
+    {{8, 1, 0, 8}, {16, 1, 8, 0}},
+    {{8, 1, 0, 8}, {16, 1, 8, 0}},
 };
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
@@ -107,7 +108,8 @@ static bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
     if (kind == 1 && (c->persist_wgs_per_cu < 1 || c->persist_wgs_per_cu > 32)) return false;
-    if (c->xcd_slabs != 0 && c->xcd_slabs != 1) return false;
+    if (c->xcd_slabs < 0 || c->xcd_slabs > 4096) return false;
+    if (kind == 1 && c->xcd_slabs > 1) return false;
     return true;
 }
 

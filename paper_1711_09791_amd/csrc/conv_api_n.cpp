@@ -27,6 +27,7 @@ int64_t fill_desc_n(ImgDev *d, const void *in, void *out, float *tmp, const conv
     conv_tile_cfg cfg{};
     cfg.rows_per_tile = direct ? kThDirectN : kThSepN;
     cfg.waves_per_wg = waves_n(img->dtype);
+    cfg.xcd_slabs = kXcdChunkRowsN / cfg.rows_per_tile;
     return fill_desc(d, in, out, tmp, img, L, kNoTaps, cfg);
 }
 

@@ -37,7 +37,8 @@ struct ImgDev {
     int32_t nsg;          // strip groups (waves_per_wg strips each)
     int32_t nb;           // row bands
     int32_t th;           // output rows per band
-    int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles
+    int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles;
+                          // c >= 2: XCDs take turns on chunks of c band rows
     int32_t reserved;
     int64_t tile_begin;   // batch: this image's first tile in the launch
     int64_t tile_end;     // batch: one past its last tile
@@ -62,7 +63,8 @@ struct TapsN {
 constexpr int kMaxWidthN = 9;
 constexpr int kThSepN = 8;     // rows per band: fused, row and column kernels
 constexpr int kThDirectN = 4;  // rows per band: direct n x n
-constexpr int waves_n(int dtype) { return dtype == 0 ? 2 : 1; }
+constexpr int waves_n(int) { return 1; }
+constexpr int kXcdChunkRowsN = 64;  // rows per XCD chunk of the width-n kernels
 
 // Elements per lane per row: 16 bytes of storage.
 inline int vec_of(int dtype) { return dtype == 0 ? 4 : 8; }

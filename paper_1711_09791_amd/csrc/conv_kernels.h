@@ -631,9 +631,23 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return xcd * q + min(xcd, r) + i;
 }
 
+// Band chunks dealt to the XCDs in turn: XCD x (blocks x, x+8, x+16, ...)
+// takes chunks x, x+8, ... of T consecutive logical tiles (c full band rows),
+// each in order, so both horizontal neighbours of a tile and the band above
+// it were read through the same L2.  Blocks past the last whole round of 8
+// chunks keep their own index.
+__device__ __forceinline__ int xcd_chunk_remap(int b, int n, int64_t T) {
+    constexpr int X = 8;
+    const int64_t full = ((int64_t)n / (X * T)) * (X * T);
+    if (b >= full) return b;
+    const int x = b % X, i = b / X;
+    return (int)((x + X * (i / T)) * T + i % T);
+}
+
 // One workgroup per logical tile; grids above 2^20 workgroups loop.  In
 // launch order (xcd_slabs = 0) the resident waves sweep the image row-band by
-// row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows.
+// row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows; with
+// xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows.
 template <class D, bool AL, int MODE, int WAVES, int TH>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -642,7 +656,10 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblock
         const int64_t left = nblocks - base;
         const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
         if ((int)blockIdx.x >= cnt) break;
-        const int b = im.xcd_slabs ? xcd_remap(blockIdx.x, cnt) : (int)blockIdx.x;
+        const int b = im.xcd_slabs == 1   ? xcd_remap(blockIdx.x, cnt)
+                      : im.xcd_slabs > 1 ? xcd_chunk_remap(blockIdx.x, cnt,
+                                                            (int64_t)im.xcd_slabs * im.nsg)
+                                         : (int)blockIdx.x;
         run_tile<D, AL, MODE, WAVES, TH>(im, base + b, wave, lane);
     }
 }
@@ -660,7 +677,7 @@ __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int G = gridDim.x;
     int64_t t, end, step;
-    if (descs[0].xcd_slabs) {
+    if (descs[0].xcd_slabs == 1) {
         const int64_t L = xcd_remap(blockIdx.x, G);
         t = total * L / G;
         end = total * (L + 1) / G;

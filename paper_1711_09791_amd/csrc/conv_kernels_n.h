@@ -289,12 +289,22 @@ __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, in
         band_n<D, AL, R, MODE, false, TH>(im, tp, plane, xs, y0, y1, lane);
 }
 
+// One workgroup per logical tile (grids above 2^20 workgroups loop); with
+// xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows, as in the
+// width-5 kernels.
 template <class D, bool AL, int R, int MODE, int WAVES, int TH>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (int64_t lt = blockIdx.x; lt < nblocks; lt += gridDim.x)
-        run_tile_n<D, AL, R, MODE, WAVES, TH>(im, tp, lt, wave, lane);
+    for (int64_t base = 0; base < nblocks; base += gridDim.x) {
+        const int64_t left = nblocks - base;
+        const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
+        if ((int)blockIdx.x >= cnt) break;
+        const int b = im.xcd_slabs > 1
+                          ? xcd_chunk_remap(blockIdx.x, cnt, (int64_t)im.xcd_slabs * im.nsg)
+                          : (int)blockIdx.x;
+        run_tile_n<D, AL, R, MODE, WAVES, TH>(im, tp, base + b, wave, lane);
+    }
 }
 
 // Band heights and workgroup widths of the width-n kernels (shared with the

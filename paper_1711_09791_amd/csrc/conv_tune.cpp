@@ -18,17 +18,18 @@ std::vector<conv_tile_cfg> candidates(int kind) {
     std::vector<conv_tile_cfg> c;
     const int ths[] = {4, 8, 16, 32, 64};
     const int waves[] = {1, 2, 4};
-    for (int x = 0; x < 2; ++x) {
-        if (kind == 0) {
+    if (kind == 0) {
+        const int xcd[] = {0, 1, 4, 8, 16};
+        for (int x : xcd)
             for (int th : ths)
                 for (int w : waves) c.push_back({th, w, 0, x});
-        } else {
-            const int persist[] = {4, 8, 16};
-            for (int th : ths)
-                for (int w : waves)
-                    for (int p : persist) c.push_back({th, w, p, x});
-        }
+        return c;
     }
+    const int persist[] = {4, 8, 16};
+    for (int x = 0; x < 2; ++x)
+        for (int th : ths)
+            for (int w : waves)
+                for (int p : persist) c.push_back({th, w, p, x});
     return c;
 }
 

@@ -78,7 +78,7 @@ def test_every_tile_shape_is_bitwise_identical():
         base = {f: gu.to_host_bits(gu.run(f, a, k)) for f in FORMS}
         for th in (1, 3, 4, 8, 17, 64, 200):
             for w in (1, 2, 4):
-                for x in (0, 1):
+                for x in (0, 1, 2, 8, 64):
                     cs.conv_set_tile_cfg(0, 0, th, w, 0, x)
                     for f in FORMS:
                         got = gu.to_host_bits(gu.run(f, a, k))
