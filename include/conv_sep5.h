@@ -223,9 +223,10 @@ conv_status conv_2d_direct(const void *d_in, void *d_out, const float *K,
  *                  waves sweep the image (or batch) as one compact window;
  *                  1: each of the 8 XCDs takes one contiguous slab of tiles
  *                  (full rows), so horizontal halos stay in that XCD's L2;
- *                  c in 2..4096 (single-image kernels only): the XCDs take
- *                  turns on chunks of c full band rows, so horizontal halos
- *                  and all but one band boundary per chunk stay in one L2
+ *                  c in 2..4096: the XCDs take turns on chunks of c full
+ *                  band rows (batch kernel: of 8c consecutive tiles), so
+ *                  horizontal halos and all but one band boundary per chunk
+ *                  stay in one L2
  */
 typedef struct {
     int32_t rows_per_tile;

@@ -109,7 +109,6 @@ static bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
     if (kind == 1 && (c->persist_wgs_per_cu < 1 || c->persist_wgs_per_cu > 32)) return false;
     if (c->xcd_slabs < 0 || c->xcd_slabs > 4096) return false;
-    if (kind == 1 && c->xcd_slabs > 1) return false;
     return true;
 }
 

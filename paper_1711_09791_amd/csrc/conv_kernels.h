@@ -667,7 +667,9 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblock
 // Persistent batch kernel: a fixed grid (a multiple of the CU count) covers
 // the launch's tiles (images in order, then plane, band, strip group).  With
 // xcd_slabs = 0 the workgroups stride over the tiles, so the resident ones
-// always work on one compact window of the batch; with xcd_slabs = 1 each
+// always work on one compact window of the batch; with xcd_slabs = c >= 2
+// each such window is cut into chunks of 8c consecutive tiles that the XCDs
+// take in turn (as in the single-image kernel); with xcd_slabs = 1 each
 // workgroup takes one contiguous run, and the runs of one XCD are adjacent.
 // The owning image of each tile is found by advancing through the descriptor
 // table's tile ranges (tiles only increase within a workgroup).
@@ -676,19 +678,31 @@ __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int G = gridDim.x;
-    int64_t t, end, step;
-    if (descs[0].xcd_slabs == 1) {
-        const int64_t L = xcd_remap(blockIdx.x, G);
-        t = total * L / G;
-        end = total * (L + 1) / G;
-        step = 1;
-    } else {
-        t = blockIdx.x;
-        end = total;
-        step = G;
+    const int b = blockIdx.x;
+    const int x = descs[0].xcd_slabs;
+    int64_t first = b, last = total;  // x == 1: this workgroup's contiguous run
+    if (x == 1) {
+        const int64_t L = xcd_remap(b, G);
+        first = total * L / G;
+        last = total * (L + 1) / G;
     }
     int i = 0;
-    for (; t < end; t += step) {
+    for (int64_t j = 0;; ++j) {
+        int64_t t;
+        if (x == 1) {
+            t = first + j;
+            if (t >= last) break;
+        } else if (x > 1) {
+            const int64_t base = j * G;
+            if (base >= total) break;
+            const int64_t left = total - base;
+            const int cnt = left < (int64_t)G ? (int)left : G;
+            if (b >= cnt) break;
+            t = base + xcd_chunk_remap(b, cnt, (int64_t)8 * x);
+        } else {
+            t = b + j * G;
+            if (t >= total) break;
+        }
         while (i < n - 1 && t >= descs[i].tile_end) ++i;
         const ImgDev &im = descs[i];
         if (im.aligned)

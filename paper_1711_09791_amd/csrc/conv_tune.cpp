@@ -26,7 +26,8 @@ std::vector<conv_tile_cfg> candidates(int kind) {
         return c;
     }
     const int persist[] = {4, 8, 16};
-    for (int x = 0; x < 2; ++x)
+    const int xcd[] = {0, 1, 8};
+    for (int x : xcd)
         for (int th : ths)
             for (int w : waves)
                 for (int p : persist) c.push_back({th, w, p, x});

@@ -157,8 +157,6 @@ def test_tile_cfg_validation_and_roundtrip():
     assert (c.rows_per_tile, c.waves_per_wg, c.persist_wgs_per_cu) == (48, 2, 6)
     with pytest.raises(cs.ConvError):
         cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 4097)   # XCD chunk out of range
-    with pytest.raises(cs.ConvError):
-        cs.conv_set_tile_cfg(0, 1, 16, 1, 8, 2)     # batch kernel: 0 or 1 only
     b16 = cs.conv_get_tile_cfg(1, 0)
     cs.conv_set_tile_cfg(1, 0, 8, 1, 0, 16)
     assert cs.conv_get_tile_cfg(1, 0).xcd_slabs == 16
