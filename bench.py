@@ -22,6 +22,8 @@ Also measured and reported in the same JSON line:
              direct (n*n terms) separable forms and a full non-separable
              n x n kernel, each against the HBM and the FP32 ALU roofline
              (the O(n) vs O(n^2) trade-off of Section 5.1);
+  pyramid    one blur + 2x decimation level of the same image (FP32, FP16):
+             input read once, a quarter of it written;
   cpu_baseline  the FP64 oracle on the host cores, on the whole image.
 
 Prints ONE JSON line.  Run with no flags for the default configuration.
@@ -61,7 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, widths, batch and serving measurements")
-    ap.add_argument("--extras", default="precision,widths,batch,serving",
+    ap.add_argument("--extras", default="precision,widths,pyramid,batch,serving",
                     help="comma list of extra measurements to run")
     ap.add_argument("--warm", action="store_true",
                     help="also time the fused form on one buffer set (cache-warm)")
@@ -236,6 +238,36 @@ def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
         res[f"n{n}"] = row
     del ins, outs, tmp
     return {"alu_peak_tflops": ALU_PEAK_TFLOPS, "steps": steps, "results": res}
+
+
+def bench_pyramid(torch, cs, host, k, args):
+    """conv_pyr_down on the 3x4096x4096 image in FP32 and FP16 storage."""
+    res = {}
+    S = max(1, args.sets)
+    L = cs.lib()
+    kk = (ctypes.c_float * 5)(*[float(v) for v in k])
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for name, dt in (("f32", torch.float32), ("f16", torch.float16)):
+        base = torch.from_numpy(host).cuda().to(dt)
+        ins = [base] + [base.clone() for _ in range(S - 1)]
+        outs = [torch.empty(P, (R + 1) // 2, (C + 1) // 2, dtype=dt, device="cuda") for _ in range(S)]
+        ii, oi = cs.image_of(base), cs.image_of(outs[0])
+        pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+        pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
+        fn = lambda i: check(cs, L.conv_pyr_down(pin[i % S], ctypes.byref(ii), pout[i % S],  # noqa: E731
+                                                 ctypes.byref(oi), kk, hs))
+        avg = timed(torch, fn, args.steps, args.warmup) / args.steps
+        esz = base.element_size()
+        nbytes = esz * P * R * C + esz * P * ((R + 1) // 2) * ((C + 1) // 2)
+        res[name] = {
+            "ms_per_step": avg,
+            "input_mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
+            "alg_bytes_per_step": nbytes,
+            "alg_GBps": nbytes / (avg * 1e-3) / 1e9,
+            "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
+        del ins, outs, base
+    return res
 
 
 def bench_batch(torch, cs, synth, args):
@@ -436,6 +468,9 @@ def main():
     if "widths" in want:
         extras["widths"] = bench_widths(torch, cs, synth, host, args)
         progress("widths done")
+    if "pyramid" in want:
+        extras["pyramid"] = bench_pyramid(torch, cs, host, k, args)
+        progress("pyramid done")
     if "batch" in want:
         extras["batch"] = bench_batch(torch, cs, synth, args)
         progress("batch done")

@@ -212,6 +212,27 @@ conv_status conv_2d_direct(const void *d_in, void *d_out, const float *K,
                            hipStream_t stream);
 
 /*
+ * One Gaussian-pyramid level: blur with the width-5 separable kernel, then
+ * keep every second row and column.  The paper names image scaling as the
+ * step of its stereo-matching application next to the convolution (Section
+ * 1) without defining it; this is the blur-then-decimate reading:
+ *     out[p][yo][xo] = B[p][2*yo][2*xo],  0 <= yo < ceil(rows/2),
+ *                                         0 <= xo < ceil(cols/2)
+ * with B the convolution of conv_sep5_1pass (same FMA chains, zero frame), so
+ * the result equals conv_sep5_1pass's output at the sampled pixels bitwise.
+ * One fused kernel: the input is read once and only the sampled outputs are
+ * computed and written (1 + 1/4 of the image's bytes).
+ *   d_in, in_img    input image (any layout accepted by conv_image)
+ *   d_out, out_img  output image: same dtype and planes, rows = ceil(rows/2),
+ *                   cols = ceil(cols/2), its own pitch and plane_stride;
+ *                   must not overlap the input (CONV_EALIAS)
+ *   k               5 FP32 taps (host array)
+ */
+conv_status conv_pyr_down(const void *d_in, const conv_image *in_img,
+                          void *d_out, const conv_image *out_img,
+                          const float k[5], hipStream_t stream);
+
+/*
  * Tile configuration (the autotuner's search space).  Results never depend on
  * it: every configuration gives bitwise identical output.
  *   rows_per_tile  output rows a wavefront walks down per tile (4..4096)

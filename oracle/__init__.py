@@ -17,6 +17,9 @@ per-plane driver of Section 5.3):
 ``conv5_twopass(A, k)``    separable two-pass form in FP64.
 ``conv_direct_n(A, K)``    Eq. 1 at odd width n with a full n x n kernel K.
 ``conv_sep_n(A, k)``       the same with K = k k^T (products in FP64, exact).
+``pyr_down(A, k)``         one pyramid level: conv5, then every second row and
+                           column (a reading: the paper names image scaling in
+                           Section 1 but does not define it).
 ``decode(bits, dtype)``    exact FP32 / FP16 / BF16 storage -> float64.
 ``round_to(x, dtype)``     float64 -> FP16 / BF16 bits, one RNE rounding.
 """
@@ -158,6 +161,14 @@ def conv_sep_n(A, k, nthreads: int = 1) -> np.ndarray:
     """
     k = np.asarray(k, dtype=np.float64).reshape(-1)
     return conv_direct_n(A, np.outer(k, k), nthreads)
+
+
+def pyr_down(A, k, nthreads: int = 1) -> np.ndarray:
+    """Blur then 2x decimation: out[p, yo, xo] = conv5(A, k)[p, 2 yo, 2 xo],
+    shape [planes, ceil(rows/2), ceil(cols/2)] (the zero frame of conv5 is
+    sampled like every other pixel)."""
+    B = conv5(A, k, nthreads)
+    return np.ascontiguousarray(B[..., ::2, ::2])
 
 
 def decode(bits: np.ndarray, dtype: str) -> np.ndarray:

@@ -82,7 +82,7 @@ _lib = None
 EXPORTS = (
     "conv_sep5_2pass", "conv_sep5_1pass", "conv_sep5_batch",
     "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
-    "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct",
+    "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct", "conv_pyr_down",
     "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_tune",
     "conv_serve_create", "conv_serve_submit", "conv_serve_poll", "conv_serve_drain",
     "conv_serve_destroy", "conv_serve_get_stats", "conv_last_error", "conv_version",
@@ -112,6 +112,7 @@ def lib():
         "conv_sepn_1pass": [vp, vp, fp, i32, imgp, ctypes.c_int, vp],
         "conv_sepn_2pass": [vp, vp, vp, fp, i32, imgp, vp],
         "conv_2d_direct": [vp, vp, fp, i32, imgp, vp],
+        "conv_pyr_down": [vp, imgp, vp, imgp, fp, vp],
         "conv_batch_plan_launch": [vp, vp],
         "conv_batch_plan_destroy": [vp],
         "conv_get_tile_cfg": [i32, i32, cfgp],
@@ -311,6 +312,18 @@ def conv_2d_direct(d_in, d_out, K, img: conv_image | None = None, stream=None):
     w, n = _kernel_nn(K)
     return _check(lib().conv_2d_direct(_ptr(d_in), _ptr(d_out), w, n, ctypes.byref(img),
                                        _stream(stream)))
+
+
+def conv_pyr_down(d_in, d_out, k, in_img: conv_image | None = None,
+                  out_img: conv_image | None = None, stream=None):
+    """One pyramid level: width-5 blur, then every second row and column.
+    d_out is [planes, ceil(rows/2), ceil(cols/2)] of d_in's dtype."""
+    if in_img is None:
+        in_img = image_of(d_in)
+    if out_img is None:
+        out_img = image_of(d_out)
+    return _check(lib().conv_pyr_down(_ptr(d_in), ctypes.byref(in_img), _ptr(d_out),
+                                      ctypes.byref(out_img), _taps(k), _stream(stream)))
 
 
 def _batch_args(ins, outs, ks, imgs):

@@ -55,6 +55,23 @@ struct BatchArgs {
     int64_t total;
 };
 
+// One pyramid level (blur + 2x decimation): input planes x rows x cols,
+// output planes x orows x ocols with orows = ceil(rows/2), ocols = ceil(cols/2);
+// each image has its own strides (elements of the storage type).
+struct PyrDev {
+    const void *in;
+    void *out;
+    int64_t in_pitch, in_ps, out_pitch, out_ps;
+    int32_t planes, rows, cols, orows, ocols;
+    int32_t aligned;      // 1: vector loads and stores allowed
+    int32_t ns;           // column strips of 64*VEC input columns
+    int32_t nb;           // bands of kThPyr output rows
+    int32_t xcd_chunk;    // >= 2: XCDs take turns on chunks of this many band rows
+    int32_t reserved;
+    float k[5];
+};
+constexpr int kThPyr = 4;
+
 // Taps of the width-n kernels (n = 2R+1 <= 9).
 struct TapsN {
     float k[9];    // separable taps k[0..n)
@@ -102,6 +119,8 @@ inline hipError_t launch_image_n(const ImgDev &im, const TapsN &tp, int dtype, i
          : dtype == 1 ? launch_image_n_f16(im, tp, radius, mode, nblocks, s)
                       : launch_image_n_bf16(im, tp, radius, mode, nblocks, s);
 }
+
+hipError_t launch_pyr(const PyrDev &pd, int dtype, int64_t nblocks, hipStream_t s);
 
 inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
                                hipStream_t s) {

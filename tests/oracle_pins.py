@@ -335,6 +335,81 @@ def failing_n_pins(convK) -> list[str]:
     return bad
 
 
+# ---- pins for one pyramid level (blur + 2x decimation) -----------------
+# Each takes ``pyr(A, k) -> out``; out[p, yo, xo] is Eq. 1 at source pixel
+# (2 yo, 2 xo), with the zero frame, for yo < ceil(R/2), xo < ceil(C/2).
+
+def pin_pyr_bruteforce_tiny(pyr) -> bool:
+    """Pure-Python sums at the even source pixels, every H, W in 1..11."""
+    rng = np.random.default_rng(41)
+    k = (rng.random(5) * 2 - 1).tolist()
+    for R in range(1, 12):
+        for C in range(1, 12):
+            A = rng.random((1, R, C)) * 2 - 1
+            a = A[0].tolist()
+            Ro, Co = (R + 1) // 2, (C + 1) // 2
+            ref = [[0.0] * Co for _ in range(Ro)]
+            for yo in range(Ro):
+                for xo in range(Co):
+                    y, x = 2 * yo, 2 * xo
+                    if 2 <= y < R - 2 and 2 <= x < C - 2:
+                        ref[yo][xo] = sum(a[y + i - 2][x + j - 2] * k[i] * k[j]
+                                          for i in range(5) for j in range(5))
+            got = pyr(A, k)
+            if got.shape != (1, Ro, Co) or not np.allclose(got[0], np.array(ref), rtol=0,
+                                                           atol=1e-14):
+                return False
+    return True
+
+
+def pin_pyr_constant(pyr) -> bool:
+    """Constant c: c (sum k)^2 where the source pixel is interior, else 0."""
+    k = np.array([0.5, -0.25, 1.0, 0.125, 0.75])
+    A = np.full((2, 13, 10), 3.0)
+    got = pyr(A, k)
+    ref = np.zeros((2, 7, 5))
+    for yo in range(7):
+        for xo in range(5):
+            if 2 <= 2 * yo < 11 and 2 <= 2 * xo < 8:
+                ref[:, yo, xo] = 3.0 * k.sum() ** 2
+    return got.shape == ref.shape and bool(np.allclose(got, ref, rtol=1e-15, atol=0))
+
+
+def pin_pyr_ramp(pyr) -> bool:
+    """A = a + b y + c x: at source (2 yo, 2 xo) the closed form of the conv5
+    ramp pin, so a half-pixel shift of the sampling grid fails."""
+    k = np.array([0.05, 0.1, 0.15, 0.3, 0.4])
+    a, b, c = 0.5, 2.0, -3.0
+    R, C = 15, 18
+    yy, xx = np.meshgrid(np.arange(R), np.arange(C), indexing="ij")
+    A = (a + b * yy + c * xx)[None].astype(np.float64)
+    S = k.sum()
+    m = float(np.dot(np.arange(-2, 3), k))
+    full = np.zeros((R, C))
+    full[2:-2, 2:-2] = (S * S * (a + b * yy + c * xx) + S * m * (b + c))[2:-2, 2:-2]
+    got = pyr(A, k)
+    return bool(np.allclose(got[0], full[::2, ::2], rtol=1e-13, atol=1e-13))
+
+
+PYR_PINS = {
+    "bruteforce_tiny": pin_pyr_bruteforce_tiny,
+    "constant": pin_pyr_constant,
+    "ramp": pin_pyr_ramp,
+}
+
+
+def failing_pyr_pins(pyr) -> list[str]:
+    bad = []
+    for name, pin in PYR_PINS.items():
+        try:
+            ok = pin(pyr)
+        except Exception:
+            ok = False
+        if not ok:
+            bad.append(name)
+    return bad
+
+
 # ---- rounding / decoding pins -------------------------------------------
 
 def _bf16_table():

@@ -254,3 +254,21 @@ def test_width_n_binding_rejects_non_square_kernel():
         cs._kernel_nn([[1.0, 2.0, 3.0], [4.0, 5.0]])
     taps, n = cs._kernel_nn([[1.0] * 3] * 3)
     assert n == 3 and len(taps) == 9
+
+
+def test_pyr_down_validation():
+    L = cs.lib()
+    i = img(planes=3, rows=16, cols=16)
+    o = img(planes=3, rows=8, cols=8)
+    call = lambda a, ii, b, oo, k=K: L.conv_pyr_down(a, ctypes.byref(ii), b, ctypes.byref(oo), k, None)  # noqa: E731
+    assert call(A, i, B, img(planes=3, rows=8, cols=9)) == cs.CONV_EINVAL
+    assert call(A, i, B, img(planes=3, rows=7, cols=8)) == cs.CONV_EINVAL
+    assert call(A, i, B, img(planes=2, rows=8, cols=8)) == cs.CONV_EINVAL
+    assert call(A, i, B, img(planes=3, rows=8, cols=8, dtype=1)) == cs.CONV_EINVAL
+    assert call(A, i, B, o, k=None) == cs.CONV_EINVAL
+    assert call(0, i, B, o) == cs.CONV_EINVAL
+    assert call(A, i, A + 64, o) == cs.CONV_EALIAS
+    odd = img(planes=1, rows=7, cols=9)
+    assert call(A, odd, B, img(planes=1, rows=4, cols=4)) == cs.CONV_EINVAL
+    for e, eo in ((img(rows=0), img(rows=0, cols=8)), (img(cols=0), img(rows=8, cols=0))):
+        assert call(0, e, 0, eo) == cs.CONV_OK

@@ -68,6 +68,26 @@ def test_direct_n_rejects_even_width():
         oracle.conv_direct_n(np.zeros((1, 8, 8)), np.zeros((4, 4)))
 
 
+@pytest.mark.parametrize("name", sorted(pins.PYR_PINS))
+def test_pyr_pins(name):
+    assert pins.PYR_PINS[name](oracle.pyr_down), name
+
+
+# plausible mistakes in a decimating level: odd sampling grid, floor instead
+# of ceil for the output size, sampling before blurring
+PYR_MUTANTS = {
+    "odd_grid": lambda A, k: oracle.conv5(A, k)[..., 1::2, 1::2],
+    "floor_size": lambda A, k: oracle.conv5(A, k)[..., :np.asarray(A).shape[-2] // 2 * 2:2,
+                                                  :np.asarray(A).shape[-1] // 2 * 2:2],
+    "decimate_then_blur": lambda A, k: oracle.conv5(np.asarray(A)[..., ::2, ::2], k),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PYR_MUTANTS))
+def test_pyr_pins_reject_mutant(name):
+    assert pins.failing_pyr_pins(PYR_MUTANTS[name]), name
+
+
 def _read_golden():
     cases, lines = [], [ln.strip() for ln in open(GOLDEN) if ln.strip() and not ln.startswith("#")]
     i = 0
