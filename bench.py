@@ -22,6 +22,8 @@ Also measured and reported in the same JSON line:
              direct (n*n terms) separable forms and a full non-separable
              n x n kernel, each against the HBM and the FP32 ALU roofline
              (the O(n) vs O(n^2) trade-off of Section 5.1);
+  hwc        the same image stored pixel-interleaved (packed RGB), fused and
+             two-pass, against the planar forms;
   pyramid    one blur + 2x decimation level of the same image (FP32, FP16):
              input read once, a quarter of it written;
   cpu_baseline  the FP64 oracle on the host cores, on the whole image.
@@ -63,7 +65,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, widths, batch and serving measurements")
-    ap.add_argument("--extras", default="precision,widths,pyramid,batch,serving",
+    ap.add_argument("--extras", default="precision,widths,hwc,pyramid,batch,serving",
                     help="comma list of extra measurements to run")
     ap.add_argument("--warm", action="store_true",
                     help="also time the fused form on one buffer set (cache-warm)")
@@ -238,6 +240,40 @@ def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
         res[f"n{n}"] = row
     del ins, outs, tmp
     return {"alu_peak_tflops": ALU_PEAK_TFLOPS, "steps": steps, "results": res}
+
+
+def bench_hwc(torch, cs, host, k, args):
+    """The 3x4096x4096 FP32 image as packed RGB ([rows, cols, 3]): fused,
+    direct and two-pass forms (same bytes as the planar forms)."""
+    S = max(1, args.sets)
+    base = torch.from_numpy(host).cuda().permute(1, 2, 0).contiguous()
+    ins = [base] + [base.clone() for _ in range(S - 1)]
+    outs = [torch.empty_like(base) for _ in range(S)]
+    tmp = torch.empty(P * R * C, device="cuda")
+    L = cs.lib()
+    img = cs.image_hwc(base)
+    kk = (ctypes.c_float * 5)(*[float(v) for v in k])
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+    pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
+    ptmp = ctypes.c_void_p(tmp.data_ptr())
+    fns = {
+        "fused": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, ctypes.byref(img), 0, hs)),
+        "direct25": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, ctypes.byref(img), 1, hs)),
+        "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, ctypes.byref(img), hs)),
+    }
+    res = {}
+    for name, fn in fns.items():
+        avg = timed(torch, fn, args.steps, args.warmup) / args.steps
+        nbytes = (16 if name == "2pass" else 8) * P * R * C
+        res[name] = {
+            "ms_per_step": avg,
+            "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
+            "alg_GBps": nbytes / (avg * 1e-3) / 1e9,
+            "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        }
+    del ins, outs, tmp, base
+    return res
 
 
 def bench_pyramid(torch, cs, host, k, args):
@@ -468,6 +504,9 @@ def main():
     if "widths" in want:
         extras["widths"] = bench_widths(torch, cs, synth, host, args)
         progress("widths done")
+    if "hwc" in want:
+        extras["hwc"] = bench_hwc(torch, cs, host, k, args)
+        progress("hwc done")
     if "pyramid" in want:
         extras["pyramid"] = bench_pyramid(torch, cs, host, k, args)
         progress("pyramid done")

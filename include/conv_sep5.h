@@ -75,9 +75,17 @@ typedef enum { CONV_F32 = 0, CONV_F16 = 1, CONV_BF16 = 2 } conv_dtype;
  *                (planes-1)*plane_stride + cols <= pitch: the planes' rows
  *                side by side in one row (the row-interleaved "3R x C"
  *                layout of Section 6).  Each plane keeps its own border.
+ *                1 with 2..4 planes: planes interleaved per pixel (packed
+ *                HWC, e.g. RGB): element (p, y, x) at y*pitch + x*planes + p,
+ *                pitch >= cols*planes (0 means cols*planes).  Each channel is
+ *                convolved on its own with its own border, bitwise as in the
+ *                planar layout.  Taken by conv_sep5_1pass and conv_sep5_2pass
+ *                (the two-pass workspace then holds HWC rows); the other
+ *                entry points return CONV_EINVAL for it.
  * The fast path needs 16-byte aligned base pointers and cols, pitch and
- * plane_stride that are multiples of 16/sizeof(element); other layouts run a
- * slower element-wise path with identical results.
+ * plane_stride (HWC: cols*planes and pitch) that are multiples of
+ * 16/sizeof(element); other layouts run a slower element-wise path with
+ * identical results.
  */
 typedef struct {
     int32_t planes;

@@ -202,9 +202,30 @@ def image_of(t) -> conv_image:
     else:
         raise ValueError("image tensors are [planes, rows, cols] or [rows, cols]")
     if C > 1 and sc != 1:
-        raise ValueError("columns must be contiguous (unit stride)")
+        raise ValueError("columns must be contiguous (unit stride); use image_hwc for "
+                         "pixel-interleaved [rows, cols, planes] tensors")
+    if P > 1 and C > 1 and sp == 1:
+        raise ValueError("plane stride 1 with contiguous columns makes planes overlap")
+    if P > 1 and R == 1 and C == 1:
+        # one pixel per plane: any plane stride is the dense planar layout
+        return conv_image(int(P), 1, 1, _dtype_code(t), 1, 0)
     return conv_image(int(P), int(R), int(C), _dtype_code(t), int(sr) if R > 1 else int(C),
                       int(sp) if P > 1 else 0)
+
+
+def image_hwc(t) -> conv_image:
+    """conv_image of a pixel-interleaved [rows, cols, planes] tensor (packed
+    HWC: planes 2..4 contiguous per pixel, pixels contiguous in a row); the
+    descriptor's plane_stride is 1."""
+    if t.dim() != 3:
+        raise ValueError("HWC image tensors are [rows, cols, planes]")
+    R, C, P = (int(v) for v in t.shape)
+    if t.numel() == 0:
+        return conv_image(P, R, C, _dtype_code(t), 0, 1)
+    sr, sc, sp = t.stride()
+    if (P > 1 and sp != 1) or (C > 1 and sc != P):
+        raise ValueError("HWC tensors need contiguous pixels (strides [pitch, planes, 1])")
+    return conv_image(P, R, C, _dtype_code(t), int(sr) if R > 1 else C * P, 1)
 
 
 def _same_layout(a, b, what: str = "output") -> None:

@@ -24,7 +24,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["conv_kernels_f32.hip", "conv_kernels_f16.hip", "conv_kernels_bf16.hip",
            "conv_kernels_n_f32.hip", "conv_kernels_n_f16.hip", "conv_kernels_n_bf16.hip",
-           "conv_kernels_pyr.hip",
+           "conv_kernels_pyr.hip", "conv_kernels_hwc.hip",
            "conv_api.cpp", "conv_api_n.cpp", "conv_api_pyr.cpp", "conv_tune.cpp", "conv_serve.cpp"]
 ARCH = "gfx950"
 

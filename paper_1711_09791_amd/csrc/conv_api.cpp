@@ -51,12 +51,37 @@ conv_status check_image(const conv_image *img, Layout *L) {
     if ((int64_t)img->cols * 4 > kMaxRowBytes)
         return set_error(CONV_EINVAL, "cols %d exceed the limit %lld", img->cols,
                          (long long)(kMaxRowBytes / 4));
+    const int64_t rows = img->rows, cols = img->cols, planes = img->planes;
+    if (planes > 1 && img->plane_stride == 1) {
+        // planes interleaved per pixel (packed HWC): element (p, y, x) at
+        // y*pitch + x*planes + p
+        if (planes > kMaxHwcChannels)
+            return set_error(CONV_EINVAL, "pixel-interleaved images have 2..%d planes, not %d",
+                             kMaxHwcChannels, img->planes);
+        if (cols * planes * 4 > kMaxRowBytes)
+            return set_error(CONV_EINVAL, "cols %d x planes %d exceed the row limit", img->cols,
+                             img->planes);
+        L->hwc = true;
+        L->pitch = img->pitch == 0 ? cols * planes : img->pitch;
+        if (L->pitch < cols * planes)
+            return set_error(CONV_EINVAL, "pitch %lld < cols * planes = %lld", (long long)img->pitch,
+                             (long long)(cols * planes));
+        if (L->pitch > ((int64_t)1 << 40))
+            return set_error(CONV_EINVAL, "pitch %lld too large", (long long)L->pitch);
+        L->ps = 1;
+        L->empty = rows == 0 || cols == 0;
+        if (L->empty) {
+            L->extent_bytes = 0;
+            return CONV_OK;
+        }
+        L->extent_bytes = ((rows - 1) * L->pitch + cols * planes) * L->esz;
+        return CONV_OK;
+    }
     L->pitch = img->pitch == 0 ? img->cols : img->pitch;
     if (L->pitch < img->cols)
         return set_error(CONV_EINVAL, "pitch %lld < cols %d", (long long)img->pitch, img->cols);
     if (L->pitch > ((int64_t)1 << 40))
         return set_error(CONV_EINVAL, "pitch %lld too large", (long long)L->pitch);
-    const int64_t rows = img->rows, cols = img->cols, planes = img->planes;
     const int64_t min_ps = rows > 0 ? (rows - 1) * L->pitch + cols : 0;
     L->ps = img->plane_stride == 0 ? rows * L->pitch : img->plane_stride;
     // Planes must not overlap: either one after another (planar), or side by
@@ -143,6 +168,42 @@ int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_i
     fill_taps(&d->tp, k);
     if (L.empty) return 0;
     return (int64_t)img->planes * d->nsg * d->nb;
+}
+
+// Pixel-interleaved image: tiles are (band, strip of flat elements); the XCDs
+// take turns on chunks of 64 rows.
+int64_t fill_desc_hwc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
+                      const Layout &L, const float *k) {
+    std::memset(d, 0, sizeof *d);
+    d->in = in;
+    d->out = out;
+    d->tmp = tmp;
+    d->pitch = L.pitch;
+    d->pstride = 1;
+    d->planes = img->planes;
+    d->rows = img->rows;
+    d->cols = img->cols;
+    const int v = L.vec;
+    const int64_t wf = (int64_t)img->cols * img->planes;
+    d->aligned = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0) &&
+                 (tmp == nullptr || (uintptr_t)tmp % 16 == 0) && wf % v == 0 && L.pitch % v == 0;
+    const int out_w = hwc_out_per_strip(v, img->planes);
+    d->ns = (int)((wf + out_w - 1) / out_w);
+    d->nsg = d->ns;
+    d->th = kThHwc;
+    d->nb = (img->rows + kThHwc - 1) / kThHwc;
+    d->xcd_slabs = 64 / kThHwc;
+    fill_taps(&d->tp, k);
+    if (L.empty) return 0;
+    return (int64_t)d->nb * d->ns;
+}
+
+conv_status reject_hwc(const Layout &L, const char *what) {
+    if (!L.hwc) return CONV_OK;
+    return set_error(CONV_EINVAL,
+                     "%s does not take pixel-interleaved (plane_stride 1) images; "
+                     "conv_sep5_1pass and conv_sep5_2pass do",
+                     what);
 }
 
 // ---- per-device state --------------------------------------------------------------
@@ -264,6 +325,8 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
         if (imgs[i].dtype != dtype)
             return set_error(CONV_EINVAL, "image %d dtype %d differs from image 0 (%d)", i,
                              imgs[i].dtype, dtype);
+        if (reject_hwc(L, "the batch kernel") != CONV_OK)
+            return set_error(CONV_EINVAL, "image %d: %s", i, conv_last_error());
         if (!L.empty) {
             if (!d_in[i] || !d_out[i])
                 return set_error(CONV_EINVAL, "image %d: NULL device pointer", i);
@@ -356,8 +419,14 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     const int kmode = mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25;
     ImgDev d;
     if (!copy_back) {
-        const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
-        hipError_t e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+        hipError_t e;
+        if (L.hwc) {
+            const int64_t nblocks = fill_desc_hwc(&d, d_in, d_out, nullptr, img, L, k);
+            e = launch_hwc(d, img->dtype, kmode, nblocks, stream);
+        } else {
+            const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
+            e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+        }
         if (e != hipSuccess) return hip_error(e, "1pass kernel launch");
         return CONV_OK;
     }
@@ -369,10 +438,26 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     if (e != hipSuccess)
         return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)L.extent_bytes,
                          hipGetErrorString(e));
-    int64_t nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg);
-    e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+    int64_t nblocks;
+    if (L.hwc) {
+        nblocks = fill_desc_hwc(&d, d_in, scratch, nullptr, img, L, k);
+        e = launch_hwc(d, img->dtype, kmode, nblocks, stream);
+    } else {
+        nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg);
+        e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
+    }
     if (e == hipSuccess) {
-        nblocks = fill_desc(&d, scratch, d_out, nullptr, img, L, k, cfg);
+        // the copy is elementwise: a pixel-interleaved image copies as one
+        // plane of cols*planes elements per row
+        conv_image flat = *img;
+        Layout LF = L;
+        if (L.hwc) {
+            flat.cols = img->cols * img->planes;
+            flat.planes = 1;
+            flat.plane_stride = 0;
+            LF.ps = (int64_t)img->rows * L.pitch;
+        }
+        nblocks = fill_desc(&d, scratch, d_out, nullptr, &flat, LF, k, cfg);
         e = launch_image(d, img->dtype, MODE_COPY, cfg.waves_per_wg, nblocks, stream);
     }
     (void)hipFreeAsync(scratch, stream);
@@ -405,10 +490,16 @@ conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp, const f
     }
     const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
     ImgDev d;
-    const int64_t nblocks = fill_desc(&d, d_in, d_out, tmp, img, L, k, cfg);
-    e = launch_image(d, img->dtype, MODE_ROWPASS, cfg.waves_per_wg, nblocks, stream);
-    if (e == hipSuccess)
-        e = launch_image(d, img->dtype, MODE_COLPASS, cfg.waves_per_wg, nblocks, stream);
+    if (L.hwc) {
+        const int64_t nblocks = fill_desc_hwc(&d, d_in, d_out, tmp, img, L, k);
+        e = launch_hwc(d, img->dtype, MODE_ROWPASS, nblocks, stream);
+        if (e == hipSuccess) e = launch_hwc(d, img->dtype, MODE_COLPASS, nblocks, stream);
+    } else {
+        const int64_t nblocks = fill_desc(&d, d_in, d_out, tmp, img, L, k, cfg);
+        e = launch_image(d, img->dtype, MODE_ROWPASS, cfg.waves_per_wg, nblocks, stream);
+        if (e == hipSuccess)
+            e = launch_image(d, img->dtype, MODE_COLPASS, cfg.waves_per_wg, nblocks, stream);
+    }
     if (!d_tmp) (void)hipFreeAsync(tmp, stream);
     if (e != hipSuccess) return hip_error(e, "2pass kernel launch");
     return CONV_OK;

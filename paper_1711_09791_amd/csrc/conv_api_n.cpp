@@ -71,6 +71,7 @@ conv_status check_common(const void *d_in, void *d_out, const void *taps, int32_
                          const conv_image *img, Layout *L) {
     conv_status st = check_image(img, L);
     if (st != CONV_OK) return st;
+    if ((st = reject_hwc(*L, "the width-n entry points")) != CONV_OK) return st;
     if ((st = check_width(n)) != CONV_OK) return st;
     if (!taps) return set_error(CONV_EINVAL, "taps pointer is NULL");
     if (L->empty) return CONV_OK;

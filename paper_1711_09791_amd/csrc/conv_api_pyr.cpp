@@ -25,6 +25,8 @@ conv_status conv_pyr_down(const void *d_in, const conv_image *in_img, void *d_ou
     conv_status st = check_image(in_img, &Li);
     if (st != CONV_OK) return st;
     if ((st = check_image(out_img, &Lo)) != CONV_OK) return st;
+    if ((st = reject_hwc(Li, "conv_pyr_down")) != CONV_OK) return st;
+    if ((st = reject_hwc(Lo, "conv_pyr_down")) != CONV_OK) return st;
     if (!k) return set_error(CONV_EINVAL, "taps pointer is NULL");
     if (in_img->dtype != out_img->dtype || in_img->planes != out_img->planes)
         return set_error(CONV_EINVAL, "input and output differ in dtype or planes");

@@ -21,6 +21,7 @@ struct Layout {
     int64_t extent_bytes = 0;    // bytes from the base to one past the last element
     int esz = 4, vec = 4;
     bool empty = true;
+    bool hwc = false;            // planes interleaved per pixel (plane_stride == 1)
 };
 
 conv_status set_error(conv_status st, const char *fmt, ...);
@@ -36,6 +37,9 @@ int device_cus();
 conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, const float *k,
                         const conv_image *imgs, int mode, const conv_tile_cfg &cfg,
                         std::vector<ImgDev> *descs, int64_t *total, int *dtype_out);
+int64_t fill_desc_hwc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
+                      const Layout &L, const float *k);
+conv_status reject_hwc(const Layout &L, const char *what);
 conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
                           const conv_tile_cfg &cfg, hipStream_t s);
 

@@ -122,6 +122,18 @@ inline hipError_t launch_image_n(const ImgDev &im, const TapsN &tp, int dtype, i
 
 hipError_t launch_pyr(const PyrDev &pd, int dtype, int64_t nblocks, hipStream_t s);
 
+// Pixel-interleaved (HWC) images: planes = channels per pixel (2..4), pitch in
+// elements between rows, cols in pixels; tiles are (band of kThHwc rows,
+// strip of 64*8 flat elements), ns strips.
+constexpr int kThHwc = 8;
+constexpr int kMaxHwcChannels = 4;
+// Flat elements a strip produces: the wave's lanes minus the halo lanes
+// (ceil(2P / vec) at each end, which only load).
+constexpr int hwc_out_per_strip(int vec, int channels) {
+    return (64 - 2 * ((2 * channels + vec - 1) / vec)) * vec;
+}
+hipError_t launch_hwc(const ImgDev &im, int dtype, int mode, int64_t nblocks, hipStream_t s);
+
 inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves, int64_t nblocks,
                                hipStream_t s) {
     return dtype == 0 ? launch_image_f32(im, mode, waves, nblocks, s)

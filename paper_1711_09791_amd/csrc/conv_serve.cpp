@@ -329,6 +329,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     Layout L;
     conv_status st = check_image(img, &L);
     if (st != CONV_OK) return st;
+    if ((st = reject_hwc(L, "the server")) != CONV_OK) return st;
     if (!L.empty) {
         if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
         if (overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))

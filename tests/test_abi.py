@@ -272,3 +272,40 @@ def test_pyr_down_validation():
     assert call(A, odd, B, img(planes=1, rows=4, cols=4)) == cs.CONV_EINVAL
     for e, eo in ((img(rows=0), img(rows=0, cols=8)), (img(cols=0), img(rows=8, cols=0))):
         assert call(0, e, 0, eo) == cs.CONV_OK
+
+
+def test_hwc_descriptor_validation():
+    """plane_stride 1 with 2..4 planes is the pixel-interleaved layout."""
+    L = cs.lib()
+    ok = img(planes=3, rows=16, cols=16, plane_stride=1)      # pitch 0 -> 48
+    assert call1(ok, a=0, b=0) == cs.CONV_EINVAL                # NULL pointers, layout accepted
+    assert "NULL" in cs.conv_last_error()
+    assert call1(img(planes=5, rows=16, cols=16, plane_stride=1)) == cs.CONV_EINVAL
+    assert call1(img(planes=3, rows=16, cols=16, pitch=47, plane_stride=1)) == cs.CONV_EINVAL
+    n = 16 * 48 * 4
+    assert call1(ok, a=A, b=A + n - 4) == cs.CONV_EALIAS       # extent = rows*cols*planes
+    assert call2(ok, a=A, b=B, t=B + 4) == cs.CONV_EALIAS
+    # entry points without an HWC kernel refuse it before any HIP call
+    pin = (ctypes.c_void_p * 1)(A)
+    pout = (ctypes.c_void_p * 1)(B)
+    kk = (ctypes.c_float * 5)(1, 1, 1, 1, 1)
+    ia = (conv_image * 1)(ok)
+    assert L.conv_sep5_batch(1, pin, pout, kk, ia, 0, None) == cs.CONV_EINVAL
+    assert "pixel-interleaved" in cs.conv_last_error()
+    assert L.conv_sepn_1pass(A, B, K9, 3, ctypes.byref(ok), 0, None) == cs.CONV_EINVAL
+    o = img(planes=3, rows=8, cols=8, plane_stride=1)
+    assert L.conv_pyr_down(A, ctypes.byref(ok), B, ctypes.byref(o), K, None) == cs.CONV_EINVAL
+
+
+def test_image_hwc_binding():
+    import torch
+
+    t = torch.zeros(5, 7, 3)
+    d = cs.image_hwc(t)
+    assert (d.planes, d.rows, d.cols, d.pitch, d.plane_stride) == (3, 5, 7, 21, 1)
+    with pytest.raises(ValueError):
+        cs.image_hwc(torch.zeros(3, 5, 7).permute(1, 0, 2))
+    with pytest.raises(ValueError):
+        cs.image_of(torch.zeros(5, 7, 3).permute(2, 0, 1))       # columns not contiguous
+    with pytest.raises(ValueError):
+        cs.image_of(torch.zeros(40).as_strided((3, 5, 7), (1, 7, 1)))
