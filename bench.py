@@ -528,7 +528,8 @@ def main():
         "unit": "GB/s",
         "frac": f["alg_GBps"] / HBM_PEAK_GBS,
         "traffic": traffic_for(main_form),
-        "kernel": "k_image<F32, aligned, FUSED, 2 waves, 8-row bands>",
+        "kernel": "k_image<F32, aligned, FUSED> ({rows_per_tile}-row bands, {waves_per_wg} wave(s) per "
+                  "workgroup, XCD chunks of {xcd_slabs} bands)".format(**cs.conv_get_tile_cfg(0, 0).as_dict()),
         "alg_bytes_per_launch": f["alg_bytes_per_step"],
     }
     cpu = None
