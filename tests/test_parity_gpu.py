@@ -76,7 +76,7 @@ def test_every_tile_shape_is_bitwise_identical():
     orig = cs.conv_get_tile_cfg(0, 0)
     try:
         base = {f: gu.to_host_bits(gu.run(f, a, k)) for f in FORMS}
-        for th in (1, 3, 4, 8, 17, 64, 200):
+        for th in (1, 3, 4, 8, 16, 17, 64, 200):
             for w in (1, 2, 4):
                 for x in (0, 1, 2, 8, 64):
                     cs.conv_set_tile_cfg(0, 0, th, w, 0, x)
