@@ -247,7 +247,8 @@ conv_status conv_pyr_down(const void *d_in, const conv_image *in_img,
  *   waves_per_wg   wavefronts per workgroup, each on its own column strip
  *                  (1, 2 or 4)
  *   persist_wgs_per_cu  batch kernel: resident workgroups per compute unit
- *                  (1..32); the persistent grid is this times the CU count
+ *                  (1..32), the persistent grid being this times the CU
+ *                  count; 0: one workgroup per tile (up to 2^20 of them)
  *   xcd_slabs      0: workgroups take tiles in launch order, so the resident
  *                  waves sweep the image (or batch) as one compact window;
  *                  1: each of the 8 XCDs takes one contiguous slab of tiles

@@ -115,13 +115,14 @@ bool overlaps(const void *a, int64_t na, const void *b, int64_t nb) {
 
 // ---- tile configuration ---------------------------------------------------------
 static std::mutex g_cfg_mu;
-// Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image: 8-row
-// bands, one wave per workgroup, XCDs taking turns on chunks of 8 band rows;
-// the 64-image uneven batch); conv_tune re-derives them for a given workload.
+// Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image; the
+// 64-image uneven batch): 8-row bands, one wave per workgroup, XCDs taking
+// turns on chunks of 8 band rows (batch: of 64 tiles), and for batches one
+// workgroup per tile; conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][2] = {
-    {{8, 1, 0, 8}, {16, 1, 8, 0}},
-    {{8, 1, 0, 8}, {16, 1, 8, 0}},
-    {{8, 1, 0, 8}, {16, 1, 8, 0}},
+    {{8, 1, 0, 8}, {8, 1, 0, 8}},
+    {{8, 1, 0, 8}, {8, 1, 0, 8}},
+    {{8, 1, 0, 8}, {8, 1, 0, 8}},
 };
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
@@ -132,7 +133,7 @@ conv_tile_cfg get_cfg(int dtype, int kind) {
 static bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
-    if (kind == 1 && (c->persist_wgs_per_cu < 1 || c->persist_wgs_per_cu > 32)) return false;
+    if (kind == 1 && (c->persist_wgs_per_cu < 0 || c->persist_wgs_per_cu > 32)) return false;
     if (c->xcd_slabs < 0 || c->xcd_slabs > 4096) return false;
     return true;
 }
@@ -361,6 +362,14 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
     return CONV_OK;
 }
 
+// Batch grid: persist_wgs_per_cu workgroups per CU (a persistent grid that
+// strides over the tiles), or 0: one workgroup per tile up to 2^20.
+int batch_grid(int64_t total, int cus, const conv_tile_cfg &cfg) {
+    const int64_t cap = cfg.persist_wgs_per_cu > 0 ? (int64_t)cus * cfg.persist_wgs_per_cu
+                                                   : (int64_t)1 << 20;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+}
+
 conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
                           const conv_tile_cfg &cfg, hipStream_t s) {
     if (total == 0) return CONV_OK;
@@ -374,8 +383,7 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
         std::memcpy(a.d, descs.data(), descs.size() * sizeof(ImgDev));
         a.n = (int)descs.size();
         a.total = total;
-        const int64_t cap = (int64_t)st->cus * cfg.persist_wgs_per_cu;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+        const int grid = batch_grid(total, st->cus, cfg);
         hipError_t e = launch_batch_args(a, dtype, mode, cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
         if (e != hipSuccess) return hip_error(e, "batch kernel launch");
         return CONV_OK;
@@ -383,8 +391,7 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
     DescSlot *slot = nullptr;
     rc = stage_descs(st, descs.data(), descs.size() * sizeof(ImgDev), s, &slot);
     if (rc != CONV_OK) return rc;
-    const int64_t cap = (int64_t)st->cus * cfg.persist_wgs_per_cu;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+    const int grid = batch_grid(total, st->cus, cfg);
     hipError_t e = launch_batch((const ImgDev *)slot->dev, (int)descs.size(), total, dtype, mode,
                                 cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
     rc = finish_slot(slot, s);
@@ -591,8 +598,7 @@ conv_status conv_batch_plan_create(int32_t n, const void *const *d_in, void *con
     hipError_t le = hipSuccess;
     if (e == hipSuccess) {
         if (total > 0) {
-            const int64_t capn = (int64_t)ds->cus * cfg.persist_wgs_per_cu;
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, capn));
+            const int grid = batch_grid(total, ds->cus, cfg);
             le = launch_batch(p->d_descs, (int)descs.size(), total, dtype,
                               mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
                               cfg.waves_per_wg, cfg.rows_per_tile, grid, p->cap);

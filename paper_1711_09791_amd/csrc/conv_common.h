@@ -40,6 +40,7 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
 int64_t fill_desc_hwc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
                       const Layout &L, const float *k);
 conv_status reject_hwc(const Layout &L, const char *what);
+int batch_grid(int64_t total, int cus, const conv_tile_cfg &cfg);
 conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
                           const conv_tile_cfg &cfg, hipStream_t s);
 

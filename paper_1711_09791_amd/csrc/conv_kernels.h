@@ -671,8 +671,24 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblock
 // each such window is cut into chunks of 8c consecutive tiles that the XCDs
 // take in turn (as in the single-image kernel); with xcd_slabs = 1 each
 // workgroup takes one contiguous run, and the runs of one XCD are adjacent.
-// The owning image of each tile is found by advancing through the descriptor
-// table's tile ranges (tiles only increase within a workgroup).
+// The owning image of a workgroup's first tile is found by binary search over
+// the descriptor table's tile ranges, later ones by advancing through them
+// (tiles only increase within a workgroup).  A grid of one workgroup per tile
+// (persist_wgs_per_cu = 0) runs one iteration per workgroup.
+// The image that owns tile t: the last one whose tile range starts at or
+// before t (an empty image shares its start with the next one).
+__device__ __forceinline__ int find_image(const ImgDev *__restrict__ descs, int n, int64_t t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_begin <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <class D, int MODE, int WAVES, int TH>
 __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int n, int64_t total) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -703,7 +719,10 @@ __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int
             t = b + j * G;
             if (t >= total) break;
         }
-        while (i < n - 1 && t >= descs[i].tile_end) ++i;
+        if (j == 0)
+            i = find_image(descs, n, t);
+        else
+            while (i < n - 1 && t >= descs[i].tile_end) ++i;
         const ImgDev &im = descs[i];
         if (im.aligned)
             run_tile<D, true, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);

@@ -25,7 +25,7 @@ std::vector<conv_tile_cfg> candidates(int kind) {
                 for (int w : waves) c.push_back({th, w, 0, x});
         return c;
     }
-    const int persist[] = {4, 8, 16};
+    const int persist[] = {0, 4, 8, 16};
     const int xcd[] = {0, 1, 8};
     for (int x : xcd)
         for (int th : ths)

@@ -149,7 +149,7 @@ def test_tile_cfg_validation_and_roundtrip():
     with pytest.raises(cs.ConvError):
         cs.conv_set_tile_cfg(0, 0, 32, 3)
     with pytest.raises(cs.ConvError):
-        cs.conv_set_tile_cfg(0, 1, 32, 1, 0)
+        cs.conv_set_tile_cfg(0, 1, 32, 1, 33)
     with pytest.raises(cs.ConvError):
         cs.conv_get_tile_cfg(4, 0)
     cs.conv_set_tile_cfg(2, 1, 48, 2, 6)

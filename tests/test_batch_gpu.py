@@ -133,7 +133,7 @@ def test_every_batch_tile_config_is_bitwise_identical_and_tuner_runs():
     try:
         for th in (4, 8, 16, 64, 128):
             for w in (1, 2, 4):
-                for p in (1, 4, 16):
+                for p in (0, 1, 4, 16):
                     for x in (0, 1, 2, 8):
                         cs.conv_set_tile_cfg(0, 1, th, w, p, x)
                         outs = [gu.nan_like(a) for a in ins]
