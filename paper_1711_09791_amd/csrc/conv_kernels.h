@@ -543,29 +543,51 @@ __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs
 template <class D, bool AL>
 __device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, int y0, int y1,
                                           int lane) {
-    constexpr int VEC = D::VEC;
+    constexpr int VEC = D::VEC, G = 8;  // rows per group: all loads, then all stores
     const int x = xs + lane * VEC;
     const char *sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
     char *dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
     const int64_t stride = im.pitch * D::ESZ;
     const uint32_t rbytes = (uint32_t)im.cols * D::ESZ;
-#pragma unroll 8
-    for (int y = y0; y < y1; ++y) {
-        const auto rs = row_rsrc(sbase + (int64_t)y * stride, rbytes);
-        const auto rd = row_rsrc(dbase + (int64_t)y * stride, rbytes);
-        if constexpr (AL) {
-            const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b128(v, rd, x * D::ESZ, 0, NT);
-        } else {
+    for (int y = y0; y < y1; y += G) {
+        // the compiler keeps a load after an earlier store to a buffer that
+        // might alias it, so one load per row then its store would leave one
+        // load in flight per lane: the group's loads are issued first
+        uint32_t v[G][AL ? 4 : VEC];
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                const int off = (x + e) * D::ESZ;
-                if constexpr (D::ESZ == 4)
-                    __builtin_amdgcn_raw_buffer_store_b32(
-                        __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0), rd, off, 0, NT);
-                else
-                    __builtin_amdgcn_raw_buffer_store_b16(
-                        __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0), rd, off, 0, NT);
+        for (int i = 0; i < G; ++i) {
+            const auto rs = row_rsrc(sbase + (int64_t)min(y + i, y1 - 1) * stride, rbytes);
+            if constexpr (AL) {
+                const u4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, 0);
+                v[i][0] = q.x;
+                v[i][1] = q.y;
+                v[i][2] = q.z;
+                v[i][3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int off = (x + e) * D::ESZ;
+                    v[i][e] = D::ESZ == 4 ? __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0)
+                                          : __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (y + i >= y1) break;
+            const auto rd = row_rsrc(dbase + (int64_t)(y + i) * stride, rbytes);
+            if constexpr (AL) {
+                __builtin_amdgcn_raw_buffer_store_b128(u4{v[i][0], v[i][1], v[i][2], v[i][3]}, rd,
+                                                       x * D::ESZ, 0, NT);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int off = (x + e) * D::ESZ;
+                    if constexpr (D::ESZ == 4)
+                        __builtin_amdgcn_raw_buffer_store_b32(v[i][e], rd, off, 0, NT);
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)v[i][e], rd, off, 0, NT);
+                }
             }
         }
     }
