@@ -1,0 +1,159 @@
+/*
+ * abi_check.c -- the C ABI of libconvsep5 used from plain C with HIP device
+ * memory (no Python, no torch): fused, direct and two-pass forms, the
+ * single pass with copy-back, a two-image batch, and the error path, on a
+ * 3 x 97 x 333 image, each compared with the FP64 oracle of Eq. 1 (arXiv
+ * 1711.09791, Section 1; zero border, Section 5), which this test links as
+ * test infrastructure.
+ *
+ * Pixels are m/256 (m from a 32-bit LCG) and the taps the binomial
+ * [1,4,6,4,1]/16, so every FP32 operation is exact and every form must equal
+ * the oracle rounded to FP32 bit for bit; a second pass with unnormalised
+ * positive taps checks the 1e-6 relative bound.
+ * Prints "abi_check OK" and exits 0 on success; prints the failure and exits 1
+ * otherwise.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "conv_sep5.h"
+
+/* the oracle (oracle/conv5_oracle.c) */
+void oracle_conv5_direct(const double *A, double *B, const double *k, int64_t planes,
+                         int64_t rows, int64_t cols, int nthreads);
+
+#define P 3
+#define R 97
+#define C 333
+#define N (P * R * C)
+
+static int fail(const char *what) {
+    printf("abi_check FAILED: %s (%s)\n", what, conv_last_error());
+    return 1;
+}
+
+#define HIPCHECK(x)                                                      \
+    do {                                                                 \
+        hipError_t e_ = (x);                                             \
+        if (e_ != hipSuccess) {                                          \
+            printf("abi_check FAILED: %s: %s\n", #x, hipGetErrorString(e_)); \
+            return 1;                                                    \
+        }                                                                \
+    } while (0)
+
+/* max relative error of got vs ref; zero references must be exactly +0 */
+static double compare(const float *got, const double *ref, int exact) {
+    double worst = 0.0;
+    for (int i = 0; i < N; ++i) {
+        if (ref[i] == 0.0) {
+            if (got[i] != 0.0f || signbit(got[i])) return INFINITY;
+            continue;
+        }
+        if (exact && got[i] != (float)ref[i]) return INFINITY;
+        const double e = fabs((double)got[i] - ref[i]) / fabs(ref[i]);
+        if (e > worst) worst = e;
+    }
+    return worst;
+}
+
+int main(void) {
+    static float host[N], out[N];
+    static double a64[N], ref[N];
+    uint32_t s = 12345u;
+    for (int i = 0; i < N; ++i) {
+        s = s * 1664525u + 1013904223u;
+        host[i] = (float)(s >> 24) / 256.0f;
+        a64[i] = host[i];
+    }
+    const conv_image img = {P, R, C, CONV_F32, 0, 0};
+    const size_t bytes = sizeof(float) * N;
+    void *d_in, *d_out, *d_cb;
+    HIPCHECK(hipMalloc(&d_in, bytes));
+    HIPCHECK(hipMalloc(&d_out, bytes));
+    HIPCHECK(hipMalloc(&d_cb, bytes));
+    hipStream_t st;
+    HIPCHECK(hipStreamCreate(&st));
+    HIPCHECK(hipMemcpy(d_in, host, bytes, hipMemcpyHostToDevice));
+
+    const float tap_sets[2][5] = {{1.0f / 16, 4.0f / 16, 6.0f / 16, 4.0f / 16, 1.0f / 16},
+                                  {0.3f, 1.7f, 0.9f, 2.25f, 0.05f}};
+    for (int t = 0; t < 2; ++t) {
+        const float *k = tap_sets[t];
+        const double k64[5] = {k[0], k[1], k[2], k[3], k[4]};
+        oracle_conv5_direct(a64, ref, k64, P, R, C, 1);
+        const int exact = t == 0;
+        const char *names[4] = {"fused", "direct25", "2pass", "copy-back"};
+        for (int form = 0; form < 4; ++form) {
+            HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st)); /* NaN pattern */
+            conv_status rc;
+            void *dst = d_out;
+            if (form == 0) rc = conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_FUSED, st);
+            else if (form == 1) rc = conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_DIRECT25, st);
+            else if (form == 2) rc = conv_sep5_2pass(d_in, d_out, NULL, k, &img, st);
+            else {
+                HIPCHECK(hipMemcpyAsync(d_cb, d_in, bytes, hipMemcpyDeviceToDevice, st));
+                rc = conv_sep5_1pass(d_cb, d_cb, k, &img, CONV_1PASS_FUSED, st);
+                dst = d_cb;
+            }
+            if (rc != CONV_OK) return fail(names[form]);
+            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(hipMemcpy(out, dst, bytes, hipMemcpyDeviceToHost));
+            /* the direct form rounds K = k k^T once, so it is exact only for dyadic products */
+            const double e = compare(out, ref, exact);
+            printf("%-9s taps %d: max rel err %.3e\n", names[form], t, e);
+            if (!(e <= 1e-6)) return fail(names[form]);
+        }
+    }
+
+    /* two images in one batch launch: the image and its first plane alone */
+    {
+        const float *k = tap_sets[1];
+        const double k64[5] = {k[0], k[1], k[2], k[3], k[4]};
+        static float out2[R * C];
+        static double ref2[R * C];
+        void *d_out2;
+        HIPCHECK(hipMalloc(&d_out2, sizeof(float) * R * C));
+        const void *ins[2] = {d_in, d_in};
+        void *outs[2] = {d_out, d_out2};
+        const conv_image imgs[2] = {img, {1, R, C, CONV_F32, 0, 0}};
+        float kk[10];
+        memcpy(kk, k, sizeof(float) * 5);
+        memcpy(kk + 5, k, sizeof(float) * 5);
+        if (conv_sep5_batch(2, ins, outs, kk, imgs, CONV_1PASS_FUSED, st) != CONV_OK)
+            return fail("batch");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(out2, d_out2, sizeof(float) * R * C, hipMemcpyDeviceToHost));
+        oracle_conv5_direct(a64, ref, k64, P, R, C, 1);
+        oracle_conv5_direct(a64, ref2, k64, 1, R, C, 1);
+        if (!(compare(out, ref, 0) <= 1e-6)) return fail("batch image 0");
+        for (int i = 0; i < R * C; ++i)
+            if (out2[i] != out[i]) return fail("batch image 1 differs from plane 0 of image 0");
+        HIPCHECK(hipFree(d_out2));
+        printf("batch: OK\n");
+    }
+
+    /* errors come back as a status and a message, before any HIP call */
+    {
+        conv_image bad = img;
+        bad.dtype = 7;
+        if (conv_sep5_1pass(d_in, d_out, tap_sets[0], &bad, CONV_1PASS_FUSED, st) != CONV_EINVAL ||
+            strlen(conv_last_error()) == 0)
+            return fail("bad dtype accepted");
+        if (conv_sep5_1pass(d_in, (char *)d_in + 4, tap_sets[0], &img, CONV_1PASS_FUSED, st) !=
+            CONV_EALIAS)
+            return fail("partial overlap accepted");
+    }
+
+    HIPCHECK(hipStreamDestroy(st));
+    HIPCHECK(hipFree(d_in));
+    HIPCHECK(hipFree(d_out));
+    HIPCHECK(hipFree(d_cb));
+    printf("abi_check OK (%s)\n", conv_version());
+    return 0;
+}
