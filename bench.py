@@ -475,8 +475,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the "
-              "convolution of one image is a single-GPU kernel; multi-GPU sharding is "
-              "described in DESIGN.md and not built.", file=sys.stderr)
+              "convolution of one image is a single-GPU kernel, and sharding one image "
+              "over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

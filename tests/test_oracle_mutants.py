@@ -1,7 +1,8 @@
 """Plant mistakes in copies of the oracle (on the CPU) and check the pins catch
 each one.  This shows the pins are discriminating: a dropped term, a flipped
-or wrong index, a wrong sign or border, or a Listing-1-style row pass that
-skips the outer rows all fail at least one pin.  Nothing here touches a GPU.
+or wrong index, a wrong sign or border, or a row pass that skips the outer
+rows (the literal reading of the OpenMP listing of Section 5.3) all fail at
+least one pin.  Nothing here touches a GPU.
 """
 import ctypes
 import os
