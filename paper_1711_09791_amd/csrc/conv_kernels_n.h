@@ -142,15 +142,39 @@ __device__ __forceinline__ void hfilter_n(const float (&v)[N + 2 * R], const flo
     }
 }
 
-// Pairwise sum of p[LO..HI): split at the largest power of two below HI-LO.
-template <int LO, int HI, int M>
-__device__ __forceinline__ float pairwise(const float (&p)[M]) {
+// Direct n x n sums for a whole band: out[j][e] = pairwise sum over kernel
+// rows a of the chains sum_b w[j+a][e+b] K[a][b].  Subtrees of the pairwise
+// split are evaluated left to right and each leaf (one kernel row) for all
+// TH x VEC outputs at once, so one weight K[a][b] serves TH*VEC FMAs in a
+// row.  Each output's row partials are added pairwise, the first half of
+// every split being the largest power of two below its length.
+template <int LO, int HI, int NT_, int TH, int VEC, int WN>
+__device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], const float *K,
+                                            float (&s)[TH][VEC]) {
     if constexpr (HI - LO == 1) {
-        return p[LO];
+        constexpr int a = LO;
+#pragma unroll
+        for (int j = 0; j < TH; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[j][e] = w[j + a][e] * K[a * NT_];
+#pragma unroll
+        for (int b = 1; b < NT_; ++b) {
+            const float kab = K[a * NT_ + b];
+#pragma unroll
+            for (int j = 0; j < TH; ++j)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s[j][e] = __builtin_fmaf(w[j + a][e + b], kab, s[j][e]);
+        }
     } else {
         constexpr int n = HI - LO;
         constexpr int half = n >= 8 ? (n > 8 ? 8 : 4) : (n > 4 ? 4 : (n > 2 ? 2 : 1));
-        return pairwise<LO, LO + half, M>(p) + pairwise<LO + half, HI, M>(p);
+        float r[TH][VEC];
+        direct_tree<LO, LO + half, NT_, TH, VEC, WN>(w, K, s);
+        direct_tree<LO + half, HI, NT_, TH, VEC, WN>(w, K, r);
+#pragma unroll
+        for (int j = 0; j < TH; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[j][e] = s[j][e] + r[j][e];
     }
 }
 
@@ -234,6 +258,8 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
                 hfilter_n<VEC, R>(v, tp.k, w[i]);
             }
         }
+        float dsum[DIRECT ? TH : 1][VEC];
+        if constexpr (DIRECT) direct_tree<0, NT_, NT_, TH, VEC, WN>(w, tp.K, dsum);
 #pragma unroll
         for (int j = 0; j < TH; ++j) {
             const int y = y0 + j;
@@ -242,16 +268,7 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
                 if constexpr (DIRECT) {
-                    float p[NT_];
-#pragma unroll
-                    for (int a = 0; a < NT_; ++a) {
-                        float t = w[j + a][e] * tp.K[a * NT_];
-#pragma unroll
-                        for (int b = 1; b < NT_; ++b)
-                            t = __builtin_fmaf(w[j + a][e + b], tp.K[a * NT_ + b], t);
-                        p[a] = t;
-                    }
-                    o[e] = pairwise<0, NT_, NT_>(p);
+                    o[e] = dsum[j][e];
                 } else {
                     float t = w[j][e] * tp.k[0];
 #pragma unroll
