@@ -105,11 +105,12 @@ template <class D> struct Raw<D, false> { uint32_t e[D::VEC + 4]; };
 
 // Aligned: one 16-byte load per lane; lane 0 / lane 63 also load the two
 // elements left / right of the strip (offset `hoff`, OOB for other lanes).
-template <class D>
+// LAUX: cache policy of the row load (0, or NT for rows read only once).
+template <class D, int LAUX = 0>
 __device__ __forceinline__ void issue(Raw<D, true> &r, const char *row, uint32_t rbytes, int x,
                                       int hoff) {
     const auto rs = row_rsrc(row, rbytes);
-    r.m = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, 0);
+    r.m = __builtin_amdgcn_raw_buffer_load_b128(rs, x * D::ESZ, 0, LAUX);
     if constexpr (D::ESZ == 4) {
         const u2 h = __builtin_amdgcn_raw_buffer_load_b64(rs, hoff, 0, 0);
         r.h0 = h.x;
@@ -121,7 +122,7 @@ __device__ __forceinline__ void issue(Raw<D, true> &r, const char *row, uint32_t
 }
 // Unaligned layouts: element loads of columns x-2 .. x+VEC+1; columns left
 // of 0 get an explicit out-of-range offset, columns >= W fail the range check.
-template <class D>
+template <class D, int LAUX = 0>
 __device__ __forceinline__ void issue(Raw<D, false> &r, const char *row, uint32_t rbytes, int x,
                                       int) {
     const auto rs = row_rsrc(row, rbytes);
@@ -191,7 +192,10 @@ __device__ __forceinline__ void issue_t(RawT<N, AL> &r, const char *row, uint32_
     }
 }
 
-template <int N, bool AL>
+// SAUX: cache policy of the stores (NT streams them out; 0 keeps the FP32
+// intermediate of the two-pass form cached for the column kernel that reads
+// it next).
+template <int N, bool AL, int SAUX = NT>
 __device__ __forceinline__ void store_t(char *row, uint32_t rbytes, int x, const float (&o)[N]) {
     const auto rs = row_rsrc(row, rbytes);
     if constexpr (AL) {
@@ -199,12 +203,12 @@ __device__ __forceinline__ void store_t(char *row, uint32_t rbytes, int x, const
         for (int j = 0; j < N / 4; ++j) {
             const u4 q = {__float_as_uint(o[4 * j]), __float_as_uint(o[4 * j + 1]),
                           __float_as_uint(o[4 * j + 2]), __float_as_uint(o[4 * j + 3])};
-            __builtin_amdgcn_raw_buffer_store_b128(q, rs, (x + 4 * j) * 4, 0, NT);
+            __builtin_amdgcn_raw_buffer_store_b128(q, rs, (x + 4 * j) * 4, 0, SAUX);
         }
     } else {
 #pragma unroll
         for (int e = 0; e < N; ++e)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[e]), rs, (x + e) * 4, 0, NT);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[e]), rs, (x + e) * 4, 0, SAUX);
     }
 }
 
@@ -480,10 +484,12 @@ struct RBand {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
     }
+    // each input row is read once by the row kernel: streamed
     __device__ __forceinline__ void fetch(Raw<D, AL> &r, int row) const {
-        issue<D>(r, sbase + (int64_t)row * sstride, sbytes, x, hoff);
+        issue<D, NT>(r, sbase + (int64_t)row * sstride, sbytes, x, hoff);
     }
-    // T[row] = horizontal filter on columns 2..W-3, 0 elsewhere.
+    // T[row] = horizontal filter on columns 2..W-3, 0 elsewhere; T stays
+    // cached for the column kernel.
     __device__ __forceinline__ void filter_store(const Raw<D, AL> &r, int row) const {
         float v[VEC + 4], h[VEC];
         decode<D>(r, v);
@@ -492,7 +498,7 @@ struct RBand {
 #pragma unroll
             for (int i = 0; i < VEC; ++i) h[i] = cm[i] ? h[i] : 0.0f;
         }
-        store_t<VEC, AL>(tbase + (int64_t)row * tstride, tbytes, x, h);
+        store_t<VEC, AL, 0>(tbase + (int64_t)row * tstride, tbytes, x, h);
     }
 };
 

@@ -134,8 +134,8 @@ __device__ __forceinline__ void band_h(const ImgDev &im, int xs, int y0, int y1,
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) h[e] = cm[e] ? h[e] : 0.0f;
             }
-            if (producer && y0 + i < y1)
-                store_t<VEC, AL>(tbase + (int64_t)(y0 + i) * WF * 4, (uint32_t)WF * 4, x, h);
+            if (producer && y0 + i < y1)  // T stays cached for the column kernel
+                store_t<VEC, AL, 0>(tbase + (int64_t)(y0 + i) * WF * 4, (uint32_t)WF * 4, x, h);
         }
         return;
     } else {

@@ -211,8 +211,8 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) h[e] = cm[e] ? h[e] : 0.0f;
             }
-            if (y0 + i < y1)
-                store_t<VEC, AL>(tbase + (int64_t)(y0 + i) * W * 4, (uint32_t)W * 4, x, h);
+            if (y0 + i < y1)  // T stays cached for the column kernel
+                store_t<VEC, AL, 0>(tbase + (int64_t)(y0 + i) * W * 4, (uint32_t)W * 4, x, h);
         }
         return;
     } else {
