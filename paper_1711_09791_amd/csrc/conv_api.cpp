@@ -445,12 +445,15 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     if (e != hipSuccess)
         return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)L.extent_bytes,
                          hipGetErrorString(e));
+    // the scratch is written with cached stores: the copy reads it next
     int64_t nblocks;
     if (L.hwc) {
         nblocks = fill_desc_hwc(&d, d_in, scratch, nullptr, img, L, k);
+        d.keep_out = 1;
         e = launch_hwc(d, img->dtype, kmode, nblocks, stream);
     } else {
         nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg);
+        d.keep_out = 1;
         e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
     }
     if (e == hipSuccess) {

@@ -56,6 +56,7 @@ conv_status run_single(const void *d_in, void *d_out, const TapsN &tp, int n,
         return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)L.extent_bytes,
                          hipGetErrorString(e));
     int64_t nblocks = fill_desc_n(&d, d_in, scratch, nullptr, img, L, direct);
+    d.keep_out = 1;  // cached stores: the copy reads the scratch next
     e = launch_image_n(d, tp, img->dtype, radius, kmode, nblocks, stream);
     if (e == hipSuccess) {
         const conv_tile_cfg cfg = get_cfg(img->dtype, 0);

@@ -39,7 +39,7 @@ struct ImgDev {
     int32_t th;           // output rows per band
     int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles;
                           // c >= 2: XCDs take turns on chunks of c band rows
-    int32_t reserved;
+    int32_t keep_out;     // 1: output stores stay cached (copy-back scratch read next)
     int64_t tile_begin;   // batch: this image's first tile in the launch
     int64_t tile_end;     // batch: one past its last tile
     Taps tp;

@@ -213,7 +213,9 @@ __device__ __forceinline__ void store_t(char *row, uint32_t rbytes, int x, const
 }
 
 // ---- output rows in the storage type ------------------------------------
-template <class D, bool AL>
+// SAUX: cache policy (NT streams the output out; 0 keeps it cached when the
+// next kernel reads it, as the copy of the copy-back single pass does).
+template <class D, bool AL, int SAUX = NT>
 __device__ __forceinline__ void store_out(char *row, uint32_t rbytes, int x,
                                           const float (&o)[D::VEC]) {
     const auto rs = row_rsrc(row, rbytes);
@@ -225,17 +227,17 @@ __device__ __forceinline__ void store_out(char *row, uint32_t rbytes, int x,
 #pragma unroll
             for (int i = 0; i < 4; ++i) q[i] = enc2(D{}, o[2 * i], o[2 * i + 1]);
         }
-        __builtin_amdgcn_raw_buffer_store_b128(q, rs, x * D::ESZ, 0, NT);
+        __builtin_amdgcn_raw_buffer_store_b128(q, rs, x * D::ESZ, 0, SAUX);
     } else if constexpr (D::ESZ == 4) {
 #pragma unroll
         for (int e = 0; e < D::VEC; ++e)
-            __builtin_amdgcn_raw_buffer_store_b32(enc(D{}, o[e]), rs, (x + e) * 4, 0, NT);
+            __builtin_amdgcn_raw_buffer_store_b32(enc(D{}, o[e]), rs, (x + e) * 4, 0, SAUX);
     } else {
 #pragma unroll
         for (int e = 0; e < D::VEC; e += 2) {
             const uint32_t w = enc2(D{}, o[e], o[e + 1]);
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w & 0xffffu), rs, (x + e) * 2, 0, NT);
-            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w >> 16), rs, (x + e + 1) * 2, 0, NT);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w & 0xffffu), rs, (x + e) * 2, 0, SAUX);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w >> 16), rs, (x + e + 1) * 2, 0, SAUX);
         }
     }
 }
@@ -302,7 +304,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // (fused, direct25 and the two-pass column kernel)
 // EDGE = false: the tile touches no border row or column, so no output of it
 // needs the zero frame and the selects are compiled out.
-template <class D, bool AL, int MODE, bool EDGE>
+template <class D, bool AL, int MODE, bool EDGE, int SAUX = NT>
 struct VBand {
     static constexpr int VEC = D::VEC;
     static constexpr bool DIRECT = MODE == MODE_DIRECT25;
@@ -376,17 +378,17 @@ struct VBand {
 #pragma unroll
             for (int i = 0; i < VEC; ++i) o[i] = (vr && cm[i]) ? o[i] : 0.0f;
         }
-        store_out<D, AL>(dbase + (int64_t)y * dstride, dbytes, x, o);
+        store_out<D, AL, SAUX>(dbase + (int64_t)y * dstride, dbytes, x, o);
     }
 };
 
 // Band of compile-time height TH: all TH+4 input rows are issued first.
 // Rows outside [0, H) are clamped; they only feed border outputs (y < 2 or
 // y >= H-2), which are written as zeros.
-template <class D, bool AL, int MODE, bool EDGE, int TH>
+template <class D, bool AL, int MODE, bool EDGE, int TH, int SAUX = NT>
 __device__ __forceinline__ void band_vertical_fixed(const ImgDev &im, int plane, int xs, int y0,
                                                     int lane) {
-    using B = VBand<D, AL, MODE, EDGE>;
+    using B = VBand<D, AL, MODE, EDGE, SAUX>;
     const B b(im, plane, xs, lane);
     const int Hm1 = b.H - 1;
     typename B::RawIn raw[TH + 4];
@@ -400,10 +402,10 @@ __device__ __forceinline__ void band_vertical_fixed(const ImgDev &im, int plane,
 }
 
 // Band of any height: walk down with a 5-row window and a 5-row prefetch ring.
-template <class D, bool AL, int MODE, bool EDGE>
+template <class D, bool AL, int MODE, bool EDGE, int SAUX = NT>
 __device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int xs, int y0, int y1,
                                               int lane) {
-    using B = VBand<D, AL, MODE, EDGE>;
+    using B = VBand<D, AL, MODE, EDGE, SAUX>;
     const B b(im, plane, xs, lane);
     const int rlim = min(y1 + 1, b.H - 1);
     auto fetch = [&](typename B::RawIn &r, int row) { b.fetch(r, clampi(row, 0, rlim)); };
@@ -603,7 +605,7 @@ __device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, i
 // Logical tile lt = (plane, band, strip group), strip group fastest.  Wave
 // `wave` of the workgroup takes strip sg*WAVES + wave of the group.  TH > 0:
 // full bands of TH rows use the unrolled form (the host then sets th = TH).
-template <class D, bool AL, int MODE, bool EDGE, int TH>
+template <class D, bool AL, int MODE, bool EDGE, int TH, int SAUX = NT>
 __device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, int y0, int y1,
                                          int lane) {
     if constexpr (MODE == MODE_COPY) {
@@ -619,15 +621,15 @@ __device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, in
     } else {
         if constexpr (TH > 0) {
             if (y1 - y0 == TH) {
-                band_vertical_fixed<D, AL, MODE, EDGE, TH>(im, plane, xs, y0, lane);
+                band_vertical_fixed<D, AL, MODE, EDGE, TH, SAUX>(im, plane, xs, y0, lane);
                 return;
             }
         }
-        band_vertical<D, AL, MODE, EDGE>(im, plane, xs, y0, y1, lane);
+        band_vertical<D, AL, MODE, EDGE, SAUX>(im, plane, xs, y0, y1, lane);
     }
 }
 
-template <class D, bool AL, int MODE, int WAVES, int TH>
+template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT>
 __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave, int lane) {
     const int sg = (int)(lt % im.nsg);
     const int64_t t = lt / im.nsg;
@@ -645,9 +647,9 @@ __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave,
     if constexpr (MODE == MODE_COPY)
         run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
     else if (col_edge || row_edge)
-        run_band<D, AL, MODE, true, TH>(im, plane, xs, y0, y1, lane);
+        run_band<D, AL, MODE, true, TH, SAUX>(im, plane, xs, y0, y1, lane);
     else
-        run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
+        run_band<D, AL, MODE, false, TH, SAUX>(im, plane, xs, y0, y1, lane);
 }
 
 // Workgroups are handed to the 8 XCDs round-robin (block b -> XCD b % 8).
@@ -675,8 +677,9 @@ __device__ __forceinline__ int xcd_chunk_remap(int b, int n, int64_t T) {
 // One workgroup per logical tile; grids above 2^20 workgroups loop.  In
 // launch order (xcd_slabs = 0) the resident waves sweep the image row-band by
 // row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows; with
-// xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows.
-template <class D, bool AL, int MODE, int WAVES, int TH>
+// xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows.  SAUX is
+// the cache policy of the output stores.
+template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -688,7 +691,7 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblock
                       : im.xcd_slabs > 1 ? xcd_chunk_remap(blockIdx.x, cnt,
                                                             (int64_t)im.xcd_slabs * im.nsg)
                                          : (int)blockIdx.x;
-        run_tile<D, AL, MODE, WAVES, TH>(im, base + b, wave, lane);
+        run_tile<D, AL, MODE, WAVES, TH, SAUX>(im, base + b, wave, lane);
     }
 }
 
@@ -777,16 +780,26 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_batch_args(BatchArgs) {
 }
 
 // ---- launchers -------------------------------------------------------------------
-template <class D, bool AL, int MODE, int WAVES>
-hipError_t launch_image_th(const ImgDev &im, int64_t nblocks, hipStream_t s) {
+template <class D, bool AL, int MODE, int WAVES, int SAUX>
+hipError_t launch_image_th_p(const ImgDev &im, int64_t nblocks, hipStream_t s) {
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     const dim3 blk(WAVE * WAVES);
     switch (im.th) {
-    case 4: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4>), dim3(grid), blk, 0, s, im, nblocks); break;
-    case 8: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8>), dim3(grid), blk, 0, s, im, nblocks); break;
-    default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0>), dim3(grid), blk, 0, s, im, nblocks); break;
+    case 4: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
+    case 8: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
+    default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
     }
     return hipGetLastError();
+}
+
+// keep_out (the copy-back scratch, read by the copy next): cached output
+// stores, compiled as kernels of their own so the streaming ones are unchanged
+template <class D, bool AL, int MODE, int WAVES>
+hipError_t launch_image_th(const ImgDev &im, int64_t nblocks, hipStream_t s) {
+    if constexpr (MODE == MODE_FUSED || MODE == MODE_DIRECT25) {
+        if (im.keep_out) return launch_image_th_p<D, AL, MODE, WAVES, 0>(im, nblocks, s);
+    }
+    return launch_image_th_p<D, AL, MODE, WAVES, NT>(im, nblocks, s);
 }
 
 template <class D, bool AL, int MODE>

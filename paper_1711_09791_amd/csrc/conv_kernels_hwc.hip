@@ -90,7 +90,7 @@ __device__ __forceinline__ void window_h(const float (&u)[D::VEC], float (&v)[Hw
 
 // One band of TH rows of one strip: lane l loads flat elements x .. x+VEC-1
 // (x = xs - HL*VEC + l*VEC) and, for HL <= l < 64-HL, produces them.
-template <class D, bool AL, int P, int MODE, bool EDGE, int TH>
+template <class D, bool AL, int P, int MODE, bool EDGE, int TH, int SAUX = NT>
 __device__ __forceinline__ void band_h(const ImgDev &im, int xs, int y0, int y1, int lane) {
     using G = HwcGeom<D, P>;
     constexpr int VEC = G::VEC, HL = G::HL, E = G::E;
@@ -209,7 +209,7 @@ __device__ __forceinline__ void band_h(const ImgDev &im, int xs, int y0, int y1,
                 for (int e = 0; e < VEC; ++e) o[e] = (vr && cm[e]) ? o[e] : 0.0f;
             }
             // end lanes store nothing: an empty range drops their stores
-            store_out<D, AL>(dbase + (int64_t)y * dstride, producer ? (uint32_t)WF * D::ESZ : 0u,
+            store_out<D, AL, SAUX>(dbase + (int64_t)y * dstride, producer ? (uint32_t)WF * D::ESZ : 0u,
                              x, o);
         }
     }
@@ -217,7 +217,7 @@ __device__ __forceinline__ void band_h(const ImgDev &im, int xs, int y0, int y1,
 
 // Logical tile (band, strip), strip fastest; one wave per workgroup; XCDs
 // take turns on chunks of im.xcd_slabs band rows when that is >= 2.
-template <class D, bool AL, int P, int MODE, int TH>
+template <class D, bool AL, int P, int MODE, int TH, int SAUX = NT>
 __global__ __launch_bounds__(WAVE) void k_hwc(ImgDev im, int64_t nblocks) {
     using G = HwcGeom<D, P>;
     const int lane = threadIdx.x;
@@ -238,9 +238,9 @@ __global__ __launch_bounds__(WAVE) void k_hwc(ImgDev im, int64_t nblocks) {
         const bool col_edge = xs < 2 * P || xs + G::OUT > WF - 2 * P;
         const bool row_edge = MODE != MODE_ROWPASS && (y0 < 2 || y0 + TH > im.rows - 2);
         if (col_edge || row_edge)
-            band_h<D, AL, P, MODE, true, TH>(im, xs, y0, y1, lane);
+            band_h<D, AL, P, MODE, true, TH, SAUX>(im, xs, y0, y1, lane);
         else
-            band_h<D, AL, P, MODE, false, TH>(im, xs, y0, y1, lane);
+            band_h<D, AL, P, MODE, false, TH, SAUX>(im, xs, y0, y1, lane);
     }
 }
 
@@ -248,13 +248,25 @@ template <class D, bool AL, int P>
 hipError_t launch_hwc_p(const ImgDev &im, int mode, int64_t nblocks, hipStream_t s) {
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     constexpr int TH = kThHwc;
+    // keep_out (the copy-back scratch): cached output stores in kernels of
+    // their own
+    const bool keep = im.keep_out != 0;
     switch (mode) {
     case MODE_FUSED:
-        hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_FUSED, TH>), dim3(grid), dim3(WAVE), 0, s, im, nblocks);
+        if (keep)
+            hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_FUSED, TH, 0>), dim3(grid), dim3(WAVE), 0, s, im,
+                               nblocks);
+        else
+            hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_FUSED, TH>), dim3(grid), dim3(WAVE), 0, s, im,
+                               nblocks);
         break;
     case MODE_DIRECT25:
-        hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_DIRECT25, TH>), dim3(grid), dim3(WAVE), 0, s, im,
-                           nblocks);
+        if (keep)
+            hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_DIRECT25, TH, 0>), dim3(grid), dim3(WAVE), 0, s,
+                               im, nblocks);
+        else
+            hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_DIRECT25, TH>), dim3(grid), dim3(WAVE), 0, s, im,
+                               nblocks);
         break;
     case MODE_ROWPASS:
         hipLaunchKernelGGL((k_hwc<D, AL, P, MODE_ROWPASS, TH>), dim3(grid), dim3(WAVE), 0, s, im,

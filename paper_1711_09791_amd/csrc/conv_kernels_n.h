@@ -181,7 +181,7 @@ __device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], 
 // ---- one band ---------------------------------------------------------------------
 // MODE: MODE_FUSED (separable, register window), MODE_DIRECT25 (direct n x n
 // with tp.K), MODE_ROWPASS / MODE_COLPASS (two-pass kernels).
-template <class D, bool AL, int R, int MODE, bool EDGE, int TH>
+template <class D, bool AL, int R, int MODE, bool EDGE, int TH, int SAUX = NT>
 __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int plane, int xs, int y0,
                                        int y1, int lane) {
     constexpr int VEC = D::VEC;
@@ -281,12 +281,12 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) o[e] = (vr && cm[e]) ? o[e] : 0.0f;
             }
-            store_out<D, AL>(dbase + (int64_t)y * dstride, (uint32_t)W * D::ESZ, x, o);
+            store_out<D, AL, SAUX>(dbase + (int64_t)y * dstride, (uint32_t)W * D::ESZ, x, o);
         }
     }
 }
 
-template <class D, bool AL, int R, int MODE, int WAVES, int TH>
+template <class D, bool AL, int R, int MODE, int WAVES, int TH, int SAUX = NT>
 __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, int64_t lt, int wave,
                                            int lane) {
     const int sg = (int)(lt % im.nsg);
@@ -301,15 +301,15 @@ __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, in
     const bool col_edge = xs < R || xs + WAVE * D::VEC > im.cols - R;
     const bool row_edge = MODE != MODE_ROWPASS && (y0 < R || y0 + TH > im.rows - R);
     if (col_edge || row_edge)
-        band_n<D, AL, R, MODE, true, TH>(im, tp, plane, xs, y0, y1, lane);
+        band_n<D, AL, R, MODE, true, TH, SAUX>(im, tp, plane, xs, y0, y1, lane);
     else
-        band_n<D, AL, R, MODE, false, TH>(im, tp, plane, xs, y0, y1, lane);
+        band_n<D, AL, R, MODE, false, TH, SAUX>(im, tp, plane, xs, y0, y1, lane);
 }
 
 // One workgroup per logical tile (grids above 2^20 workgroups loop); with
 // xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows, as in the
 // width-5 kernels.
-template <class D, bool AL, int R, int MODE, int WAVES, int TH>
+template <class D, bool AL, int R, int MODE, int WAVES, int TH, int SAUX = NT>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, in
         const int b = im.xcd_slabs > 1
                           ? xcd_chunk_remap(blockIdx.x, cnt, (int64_t)im.xcd_slabs * im.nsg)
                           : (int)blockIdx.x;
-        run_tile_n<D, AL, R, MODE, WAVES, TH>(im, tp, base + b, wave, lane);
+        run_tile_n<D, AL, R, MODE, WAVES, TH, SAUX>(im, tp, base + b, wave, lane);
     }
 }
 
@@ -337,6 +337,15 @@ hipError_t launch_n_m(const ImgDev &im, const TapsN &tp, int64_t nblocks, hipStr
     constexpr int W = GeomN<D>::WAVES;
     constexpr int TH = MODE == MODE_DIRECT25 ? GeomN<D>::TH_DIRECT : GeomN<D>::TH_SEP;
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
+    // keep_out (the copy-back scratch): cached output stores in kernels of
+    // their own
+    if constexpr (MODE == MODE_FUSED || MODE == MODE_DIRECT25) {
+        if (im.keep_out) {
+            hipLaunchKernelGGL((k_image_n<D, AL, R, MODE, W, TH, 0>), dim3(grid), dim3(WAVE * W), 0, s,
+                               im, tp, nblocks);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_image_n<D, AL, R, MODE, W, TH>), dim3(grid), dim3(WAVE * W), 0, s, im, tp,
                        nblocks);
     return hipGetLastError();
