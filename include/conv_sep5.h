@@ -257,12 +257,19 @@ conv_status conv_pyr_down(const void *d_in, const conv_image *in_img,
  *                  band rows (batch kernel: of 8c consecutive tiles), so
  *                  horizontal halos and all but one band boundary per chunk
  *                  stay in one L2
+ *   pack_tail      fused (and FP32 direct25) launches with one wave per
+ *                  workgroup and 4- or 8-row bands, aligned images: a last
+ *                  column strip of at most a half (quarter) of a wave's width
+ *                  is taken by one wave for 2 (4) bands at once.
+ *                  0: when the launch has more tiles than the GPU holds at
+ *                  once (16 per compute unit); 1: always; -1: never
  */
 typedef struct {
     int32_t rows_per_tile;
     int32_t waves_per_wg;
     int32_t persist_wgs_per_cu;
     int32_t xcd_slabs;
+    int32_t pack_tail;
 } conv_tile_cfg;
 
 /* kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel. */

@@ -38,7 +38,8 @@ class conv_image(ctypes.Structure):
 
 class conv_tile_cfg(ctypes.Structure):
     _fields_ = [("rows_per_tile", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
-                ("persist_wgs_per_cu", ctypes.c_int32), ("xcd_slabs", ctypes.c_int32)]
+                ("persist_wgs_per_cu", ctypes.c_int32), ("xcd_slabs", ctypes.c_int32),
+                ("pack_tail", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -410,9 +411,9 @@ def conv_get_tile_cfg(dtype: int, kind: int) -> conv_tile_cfg:
 
 
 def conv_set_tile_cfg(dtype: int, kind: int, rows_per_tile: int, waves_per_wg: int,
-                      persist_wgs_per_cu: int = 0, xcd_slabs: int = 0):
+                      persist_wgs_per_cu: int = 0, xcd_slabs: int = 0, pack_tail: int = 0):
     c = conv_tile_cfg(int(rows_per_tile), int(waves_per_wg), int(persist_wgs_per_cu),
-                      int(xcd_slabs))
+                      int(xcd_slabs), int(pack_tail))
     return _check(lib().conv_set_tile_cfg(int(dtype), int(kind), ctypes.byref(c)))
 
 

@@ -120,9 +120,9 @@ static std::mutex g_cfg_mu;
 // turns on chunks of 8 band rows (batch: of 64 tiles), and for batches one
 // workgroup per tile; conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][2] = {
-    {{8, 1, 0, 8}, {8, 1, 0, 8}},
-    {{8, 1, 0, 8}, {8, 1, 0, 8}},
-    {{8, 1, 0, 8}, {8, 1, 0, 8}},
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
 };
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
@@ -135,6 +135,7 @@ static bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
     if (kind == 1 && (c->persist_wgs_per_cu < 0 || c->persist_wgs_per_cu > 32)) return false;
     if (c->xcd_slabs < 0 || c->xcd_slabs > 4096) return false;
+    if (c->pack_tail < -1 || c->pack_tail > 1) return false;
     return true;
 }
 
@@ -144,8 +145,22 @@ void fill_taps(Taps *t, const float *k) {
         for (int b = 0; b < 5; ++b) t->K[5 * a + b] = (float)((double)k[a] * (double)k[b]);
 }
 
+// The fused kernels of every storage type and the FP32 direct25 kernel take
+// packed last strips (mode: CONV_1PASS_*).
+bool packs_last_strip(int mode, int dtype) {
+    return mode == CONV_1PASS_FUSED || (mode == CONV_1PASS_DIRECT25 && dtype == CONV_F32);
+}
+
+// Packing only pays when the launch has more waves than the GPU holds at once
+// (16 per CU: 4 SIMDs at the kernels' occupancy of 4); below that every wave
+// starts at once and fewer of them do not end the launch sooner.
+bool pack_pays(int64_t unpacked_tiles, const conv_tile_cfg &cfg) {
+    if (cfg.pack_tail != 0) return cfg.pack_tail > 0;
+    return unpacked_tiles > (int64_t)device_cus() * 16;
+}
+
 int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
-                  const Layout &L, const float *k, const conv_tile_cfg &cfg) {
+                  const Layout &L, const float *k, const conv_tile_cfg &cfg, bool pack) {
     std::memset(d, 0, sizeof *d);
     d->in = in;
     d->out = out;
@@ -168,6 +183,18 @@ int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_i
     d->xcd_slabs = cfg.xcd_slabs;
     fill_taps(&d->tp, k);
     if (L.empty) return 0;
+    // A narrow last strip (at most a half or a quarter of 64*v columns) of an
+    // aligned image is packed: one wave takes it for 2 or 4 bands.  Its rows
+    // then share one buffer resource, whose span must stay below the
+    // out-of-range offset.
+    if (pack && al && cfg.waves_per_wg == 1 && (d->th == 4 || d->th == 8) && d->nb >= 2) {
+        const int r = img->cols - (d->ns - 1) * sw;
+        const int q = r <= 16 * v ? 4 : (r <= 32 * v ? 2 : 1);
+        if (q > 1 && (int64_t)(q * d->th + 4) * L.pitch * L.esz < ((int64_t)1 << 31) - 64) {
+            d->tq = q;
+            return (int64_t)img->planes * ((int64_t)d->nb * (d->ns - 1) + (d->nb + q - 1) / q);
+        }
+    }
     return (int64_t)img->planes * d->nsg * d->nb;
 }
 
@@ -317,6 +344,7 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
     };
     std::vector<Span> outs, ins;
     descs->resize(n);
+    std::vector<Layout> layouts(n);
     int64_t t = 0;
     for (int i = 0; i < n; ++i) {
         Layout L;
@@ -341,6 +369,18 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
         d.tile_begin = t;
         t += tiles;
         d.tile_end = t;
+        layouts[i] = L;
+    }
+    if (packs_last_strip(mode, dtype) && pack_pays(t, cfg)) {
+        t = 0;
+        for (int i = 0; i < n; ++i) {
+            ImgDev &d = (*descs)[i];
+            const int64_t tiles = fill_desc(&d, d_in[i], d_out[i], nullptr, &imgs[i], layouts[i],
+                                            k + 5 * i, cfg, true);
+            d.tile_begin = t;
+            t += tiles;
+            d.tile_end = t;
+        }
     }
     std::sort(outs.begin(), outs.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
     for (size_t i = 1; i < outs.size(); ++i)
@@ -360,6 +400,16 @@ conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, 
     }
     *total = t;
     return CONV_OK;
+}
+
+int batch_flags(const std::vector<ImgDev> &descs) {
+    int f = 0;
+    for (const ImgDev &d : descs) {
+        if (d.tile_end == d.tile_begin) continue;
+        if (!d.aligned) f |= kBatchAnyUnaligned;
+        if (d.tq > 1) f |= kBatchAnyPacked;
+    }
+    return f;
 }
 
 // Batch grid: persist_wgs_per_cu workgroups per CU (a persistent grid that
@@ -384,7 +434,8 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
         a.n = (int)descs.size();
         a.total = total;
         const int grid = batch_grid(total, st->cus, cfg);
-        hipError_t e = launch_batch_args(a, dtype, mode, cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
+        hipError_t e = launch_batch_args(a, dtype, mode, cfg.waves_per_wg, cfg.rows_per_tile, grid,
+                                         batch_flags(descs), s);
         if (e != hipSuccess) return hip_error(e, "batch kernel launch");
         return CONV_OK;
     }
@@ -393,7 +444,7 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
     if (rc != CONV_OK) return rc;
     const int grid = batch_grid(total, st->cus, cfg);
     hipError_t e = launch_batch((const ImgDev *)slot->dev, (int)descs.size(), total, dtype, mode,
-                                cfg.waves_per_wg, cfg.rows_per_tile, grid, s);
+                                cfg.waves_per_wg, cfg.rows_per_tile, grid, batch_flags(descs), s);
     rc = finish_slot(slot, s);
     if (e != hipSuccess) return hip_error(e, "batch kernel launch");
     return rc;
@@ -431,7 +482,9 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
             const int64_t nblocks = fill_desc_hwc(&d, d_in, d_out, nullptr, img, L, k);
             e = launch_hwc(d, img->dtype, kmode, nblocks, stream);
         } else {
-            const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
+            int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg);
+            if (packs_last_strip(mode, img->dtype) && pack_pays(nblocks, cfg))
+                nblocks = fill_desc(&d, d_in, d_out, nullptr, img, L, k, cfg, true);
             e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
         }
         if (e != hipSuccess) return hip_error(e, "1pass kernel launch");
@@ -453,6 +506,8 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
         e = launch_hwc(d, img->dtype, kmode, nblocks, stream);
     } else {
         nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg);
+        if (packs_last_strip(mode, img->dtype) && pack_pays(nblocks, cfg))
+            nblocks = fill_desc(&d, d_in, scratch, nullptr, img, L, k, cfg, true);
         d.keep_out = 1;
         e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
     }
@@ -604,7 +659,8 @@ conv_status conv_batch_plan_create(int32_t n, const void *const *d_in, void *con
             const int grid = batch_grid(total, ds->cus, cfg);
             le = launch_batch(p->d_descs, (int)descs.size(), total, dtype,
                               mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
-                              cfg.waves_per_wg, cfg.rows_per_tile, grid, p->cap);
+                              cfg.waves_per_wg, cfg.rows_per_tile, grid, batch_flags(descs),
+                              p->cap);
         }
         e = hipStreamEndCapture(p->cap, &p->graph);
     }

@@ -31,8 +31,11 @@ conv_status check_image(const conv_image *img, Layout *L);
 bool overlaps(const void *a, int64_t na, const void *b, int64_t nb);
 conv_tile_cfg get_cfg(int dtype, int kind);
 void fill_taps(Taps *t, const float *k);
+bool packs_last_strip(int mode, int dtype);
+int batch_flags(const std::vector<ImgDev> &descs);  // kBatchAny*
+// pack: the launch's kernel takes packed last strips (packs_last_strip)
 int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
-                  const Layout &L, const float *k, const conv_tile_cfg &cfg);
+                  const Layout &L, const float *k, const conv_tile_cfg &cfg, bool pack = false);
 int device_cus();
 conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, const float *k,
                         const conv_image *imgs, int mode, const conv_tile_cfg &cfg,

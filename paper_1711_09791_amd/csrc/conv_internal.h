@@ -40,6 +40,10 @@ struct ImgDev {
     int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles;
                           // c >= 2: XCDs take turns on chunks of c band rows
     int32_t keep_out;     // 1: output stores stay cached (copy-back scratch read next)
+    int32_t tq;           // fused/direct with one wave per workgroup: > 1 packs the
+                          // last (narrow) strip of tq consecutive bands into one
+                          // wave, 64/tq lanes per band; 0 or 1: no packing
+    int32_t reserved;
     int64_t tile_begin;   // batch: this image's first tile in the launch
     int64_t tile_end;     // batch: one past its last tile
     Taps tp;
@@ -87,6 +91,11 @@ constexpr int kXcdChunkRowsN = 64;  // rows per XCD chunk of the width-n kernels
 inline int vec_of(int dtype) { return dtype == 0 ? 4 : 8; }
 inline int esize_of(int dtype) { return dtype == 0 ? 4 : 2; }
 
+// Batch launch flags: the kernel variant must carry the element-wise path
+// (some image is not aligned) and the packed last strip (some image has tq > 1).
+constexpr int kBatchAnyUnaligned = 1;
+constexpr int kBatchAnyPacked = 2;
+
 // Kernel launchers, one translation unit per storage type
 // (conv_kernels_{f32,f16,bf16}.hip).  `waves` is 1, 2 or 4; bands of 4 or 8
 // rows (im.th / th) select the fully unrolled band kernels.
@@ -94,17 +103,17 @@ hipError_t launch_image_f32(const ImgDev &im, int mode, int waves, int64_t nbloc
 hipError_t launch_image_f16(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s);
 hipError_t launch_image_bf16(const ImgDev &im, int mode, int waves, int64_t nblocks, hipStream_t s);
 hipError_t launch_batch_f32(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
-                            int grid, hipStream_t s);
+                            int grid, int flags, hipStream_t s);
 hipError_t launch_batch_f16(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
-                            int grid, hipStream_t s);
+                            int grid, int flags, hipStream_t s);
 hipError_t launch_batch_bf16(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
-                             int grid, hipStream_t s);
+                            int grid, int flags, hipStream_t s);
 hipError_t launch_batch_args_f32(const BatchArgs &a, int mode, int waves, int th, int grid,
-                                 hipStream_t s);
+                                 int flags, hipStream_t s);
 hipError_t launch_batch_args_f16(const BatchArgs &a, int mode, int waves, int th, int grid,
-                                 hipStream_t s);
+                                 int flags, hipStream_t s);
 hipError_t launch_batch_args_bf16(const BatchArgs &a, int mode, int waves, int th, int grid,
-                                  hipStream_t s);
+                                 int flags, hipStream_t s);
 
 hipError_t launch_image_n_f32(const ImgDev &im, const TapsN &tp, int radius, int mode,
                              int64_t nblocks, hipStream_t s);
@@ -142,17 +151,17 @@ inline hipError_t launch_image(const ImgDev &im, int dtype, int mode, int waves,
 }
 
 inline hipError_t launch_batch(const ImgDev *d, int n, int64_t total, int dtype, int mode,
-                               int waves, int th, int grid, hipStream_t s) {
-    return dtype == 0 ? launch_batch_f32(d, n, total, mode, waves, th, grid, s)
-         : dtype == 1 ? launch_batch_f16(d, n, total, mode, waves, th, grid, s)
-                      : launch_batch_bf16(d, n, total, mode, waves, th, grid, s);
+                               int waves, int th, int grid, int flags, hipStream_t s) {
+    return dtype == 0 ? launch_batch_f32(d, n, total, mode, waves, th, grid, flags, s)
+         : dtype == 1 ? launch_batch_f16(d, n, total, mode, waves, th, grid, flags, s)
+                      : launch_batch_bf16(d, n, total, mode, waves, th, grid, flags, s);
 }
 
 inline hipError_t launch_batch_args(const BatchArgs &a, int dtype, int mode, int waves, int th,
-                                    int grid, hipStream_t s) {
-    return dtype == 0 ? launch_batch_args_f32(a, mode, waves, th, grid, s)
-         : dtype == 1 ? launch_batch_args_f16(a, mode, waves, th, grid, s)
-                      : launch_batch_args_bf16(a, mode, waves, th, grid, s);
+                                    int grid, int flags, hipStream_t s) {
+    return dtype == 0 ? launch_batch_args_f32(a, mode, waves, th, grid, flags, s)
+         : dtype == 1 ? launch_batch_args_f16(a, mode, waves, th, grid, flags, s)
+                      : launch_batch_args_bf16(a, mode, waves, th, grid, flags, s);
 }
 
 }  // namespace convsep5

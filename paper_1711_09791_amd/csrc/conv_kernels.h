@@ -601,6 +601,202 @@ __device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, i
     }
 }
 
+// ---- packed last strip (fused and direct25) ------------------------------------------
+// A last strip of r <= 64*VEC/Q columns would leave most lanes of its wave
+// idle, and a wave costs about the same time whether its lanes are busy or
+// not.  Here one wave takes that strip for Q consecutive bands (Q = 2 or 4):
+// lane group g (S = 64/Q lanes) works on band band0 + g.  The groups read
+// different rows, so the buffer resource spans the rows of all Q bands and
+// each lane adds its own row offset; the range check then no longer stops
+// lanes past the right edge, so their stores get an out-of-range offset
+// explicitly (their loads may read the next row, which only reaches outputs
+// in the zero frame).  The first and last lane of each group fetch the group's
+// halo columns.
+//
+// Horizontal neighbours inside a group, with no per-lane select (a select on
+// the lane's position lets the compiler put the move under a lane mask, and a
+// DPP move that reads a masked-off lane gets the fallback value instead):
+//   left:  row_shr:1 moves within each row of 16 lanes; a row's lane 0 keeps
+//          `old`, its own left halo.  With 4 groups the rows are the groups.
+//          With 2 groups, lanes 16 and 48 (row 1 and 3, lane 0) then take
+//          lane 15's and 47's value from a wave_shr:1 move written only to
+//          rows 1 and 3, bank 0 (lanes 16..19, 48..51; on 17..19 and 49..51
+//          it writes the value they already hold);
+//   right: wave_shl:1 as in the full strips.  The last lane of a group then
+//          holds the next group's first columns, but they only reach its
+//          outputs at columns >= W-2 (the group covers the strip's last
+//          column), which are written as zero.
+__device__ __forceinline__ uint32_t left_in_row(uint32_t src, uint32_t old) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x111, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t left_rows13_bank0(uint32_t src, uint32_t old) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xa, 0x1, false);
+}
+// q2: groups of 32 lanes (uniform across the wave)
+__device__ __forceinline__ uint32_t left_in_group(uint32_t src, uint32_t halo, bool q2) {
+    const uint32_t a = left_in_row(src, halo);
+    return q2 ? left_rows13_bank0(src, a) : a;
+}
+template <class D>
+__device__ __forceinline__ void decode_group(const Raw<D, true> &r, bool q2,
+                                             float (&v)[D::VEC + 4]) {
+    if constexpr (D::ESZ == 4) {
+        v[0] = __uint_as_float(left_in_group(r.m.z, r.h0, q2));
+        v[1] = __uint_as_float(left_in_group(r.m.w, r.h1, q2));
+        v[2] = __uint_as_float(r.m.x);
+        v[3] = __uint_as_float(r.m.y);
+        v[4] = __uint_as_float(r.m.z);
+        v[5] = __uint_as_float(r.m.w);
+        v[6] = __uint_as_float(from_right(r.m.x, r.h0));
+        v[7] = __uint_as_float(from_right(r.m.y, r.h1));
+    } else {
+        const uint32_t l = left_in_group(r.m.w, r.h0, q2);
+        const uint32_t rr = from_right(r.m.x, r.h0);
+        const uint32_t w[4] = {r.m.x, r.m.y, r.m.z, r.m.w};
+        v[0] = dec(D{}, l);
+        v[1] = dec(D{}, l >> 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[2 + 2 * i] = dec(D{}, w[i]);
+            v[3 + 2 * i] = dec(D{}, w[i] >> 16);
+        }
+        v[10] = dec(D{}, rr);
+        v[11] = dec(D{}, rr >> 16);
+    }
+}
+template <class D>
+__device__ __forceinline__ void decode_group(const Raw<D, false> &r, bool,
+                                             float (&v)[D::VEC + 4]) {
+    decode<D>(r, v);
+}
+
+// One input row of a lane group: `roff` is the row's byte offset in the
+// span resource, `hoff` the halo offset (already OOB for lanes without one).
+template <class D>
+__device__ __forceinline__ void issue_group(Raw<D, true> &r, __amdgpu_buffer_rsrc_t rs,
+                                            uint32_t roff, int x, int hoff) {
+    r.m = __builtin_amdgcn_raw_buffer_load_b128(rs, roff + x * D::ESZ, 0, 0);
+    const int h = hoff == OOB ? OOB : (int)(roff + hoff);
+    if constexpr (D::ESZ == 4) {
+        const u2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, h, 0, 0);
+        r.h0 = q.x;
+        r.h1 = q.y;
+    } else {
+        r.h0 = __builtin_amdgcn_raw_buffer_load_b32(rs, h, 0, 0);
+        r.h1 = 0;
+    }
+}
+template <class D>
+__device__ __forceinline__ void issue_group(Raw<D, false> &r, __amdgpu_buffer_rsrc_t rs,
+                                            uint32_t roff, int x, int) {
+#pragma unroll
+    for (int e = 0; e < D::VEC + 4; ++e) {
+        const int c = x - 2 + e;
+        const int off = c >= 0 ? (int)(roff + c * D::ESZ) : OOB;
+        if constexpr (D::ESZ == 4)
+            r.e[e] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        else
+            r.e[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+    }
+}
+
+// Output row of a lane group; `ok` is false for rows past the image and for
+// the lanes of a group beyond the last band.
+template <class D, bool AL, int SAUX>
+__device__ __forceinline__ void store_group(__amdgpu_buffer_rsrc_t rs, uint32_t roff, int x,
+                                            int W, bool ok, const float (&o)[D::VEC]) {
+    if constexpr (AL) {
+        u4 q;
+        if constexpr (D::ESZ == 4) {
+            q = u4{enc(D{}, o[0]), enc(D{}, o[1]), enc(D{}, o[2]), enc(D{}, o[3])};
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = enc2(D{}, o[2 * i], o[2 * i + 1]);
+        }
+        // aligned images have W % VEC == 0: a lane's vector is all in or all out
+        const int off = (ok && x < W) ? (int)(roff + x * D::ESZ) : OOB;
+        __builtin_amdgcn_raw_buffer_store_b128(q, rs, off, 0, SAUX);
+    } else if constexpr (D::ESZ == 4) {
+#pragma unroll
+        for (int e = 0; e < D::VEC; ++e) {
+            const int off = (ok && x + e < W) ? (int)(roff + (x + e) * 4) : OOB;
+            __builtin_amdgcn_raw_buffer_store_b32(enc(D{}, o[e]), rs, off, 0, SAUX);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < D::VEC; e += 2) {
+            const uint32_t w = enc2(D{}, o[e], o[e + 1]);
+            const int o0 = (ok && x + e < W) ? (int)(roff + (x + e) * 2) : OOB;
+            const int o1 = (ok && x + e + 1 < W) ? (int)(roff + (x + e + 1) * 2) : OOB;
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w & 0xffffu), rs, o0, 0, SAUX);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w >> 16), rs, o1, 0, SAUX);
+        }
+    }
+}
+
+// The packed strip starting at column xs for bands band0 .. band0+qg-1
+// (qg <= Q); every band has TH rows except possibly the image's last.
+template <class D, bool AL, int MODE, int TH, int SAUX>
+__device__ __forceinline__ void band_packed(const ImgDev &im, int plane, int xs, int band0, int qg,
+                                            int lane) {
+    constexpr int VEC = D::VEC;
+    constexpr bool DIRECT = MODE == MODE_DIRECT25;
+    constexpr int WN = DIRECT ? VEC + 4 : VEC;
+    const int H = im.rows, W = im.cols;
+    const bool q2 = im.tq == 2;
+    const int lgs = q2 ? 5 : 4;                    // log2 of the lanes per group
+    const int grp = lane >> lgs, ln = lane & ((1 << lgs) - 1);
+    const bool first = ln == 0, last = ln == (1 << lgs) - 1;
+    const int x = xs + ln * VEC;
+    const bool act = grp < qg;
+    const int y0 = (band0 + grp) * TH;
+    // rows ylo .. yhi feed the qg bands
+    const int ylo = max(band0 * TH - 2, 0);
+    const int yhi = min((band0 + qg) * TH + 1, H - 1);
+    const int64_t pb = im.pitch * D::ESZ;
+    const char *ib = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ + ylo * pb;
+    char *ob = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ + ylo * pb;
+    const uint32_t span = (uint32_t)((int64_t)(yhi - ylo) * pb + (int64_t)W * D::ESZ);
+    const auto rin = row_rsrc(ib, span);
+    const auto rout = row_rsrc(ob, span);
+    const int hl = xs - 2, hr = xs + (VEC << lgs);
+    const int hoff = first ? (hl >= 0 ? hl * D::ESZ : OOB)
+                           : (last ? (hr < W ? hr * D::ESZ : OOB) : OOB);
+
+    Raw<D, AL> raw[TH + 4];
+#pragma unroll
+    for (int i = 0; i < TH + 4; ++i) {
+        const int row = clampi(y0 - 2 + i, ylo, yhi);
+        issue_group<D>(raw[i], rin, (uint32_t)((int64_t)(row - ylo) * pb), x, hoff);
+    }
+    bool cm[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= 2) && (x + e < W - 2);
+    // each output row as soon as its five window rows exist
+    float w[TH + 4][WN];
+#pragma unroll
+    for (int i = 0; i < TH + 4; ++i) {
+        if constexpr (DIRECT) {
+            decode_group<D>(raw[i], q2, w[i]);
+        } else {
+            float v[VEC + 4];
+            decode_group<D>(raw[i], q2, v);
+            hfilter<VEC>(v, im.tp.k, w[i]);
+        }
+        if (i < 4) continue;
+        const int j = i - 4, y = y0 + j;
+        float o[VEC];
+        if constexpr (DIRECT)
+            direct25<VEC>(w[j], w[j + 1], w[j + 2], w[j + 3], w[j + 4], im.tp.K, o);
+        else
+            vfilter<VEC>(w[j], w[j + 1], w[j + 2], w[j + 3], w[j + 4], im.tp.k, o);
+        const bool vr = (y >= 2) && (y < H - 2);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) o[e] = (vr && cm[e]) ? o[e] : 0.0f;
+        store_group<D, AL, SAUX>(rout, (uint32_t)((int64_t)(y - ylo) * pb), x, W, act && y < H, o);
+    }
+}
+
 // ---- tiles -----------------------------------------------------------------------
 // Logical tile lt = (plane, band, strip group), strip group fastest.  Wave
 // `wave` of the workgroup takes strip sg*WAVES + wave of the group.  TH > 0:
@@ -629,14 +825,61 @@ __device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, in
     }
 }
 
-template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT>
+template <class D, bool AL, int MODE, int TH, int SAUX>
+__device__ __forceinline__ void run_strip_band(const ImgDev &im, int plane, int strip, int band,
+                                               int lane);
+
+// Tiles of an image whose last strip is packed (im.tq = Q > 1): per plane, the
+// bands go in groups of Q; a group's tiles are the m = ns-1 full strips of
+// each of its bands (band-major, strip fastest), then one packed tile for the
+// last strip of all its bands.
+template <class D, bool AL, int MODE, int TH, int SAUX>
+__device__ __forceinline__ void run_tile_packed(const ImgDev &im, int64_t lt, int lane) {
+    const int Q = im.tq, m = im.ns - 1;
+    const int64_t G = (int64_t)Q * m + 1;
+    const int64_t TP = (int64_t)im.nb * m + (im.nb + Q - 1) / Q;
+    const int plane = (int)(lt / TP);
+    const int64_t r = lt % TP;
+    const int g = (int)(r / G);
+    const int rr = (int)(r % G);
+    const int qg = min(Q, im.nb - g * Q);
+    if (rr < qg * m)
+        run_strip_band<D, AL, MODE, TH, SAUX>(im, plane, rr % m, g * Q + rr / m, lane);
+    else
+        band_packed<D, AL, MODE, TH, SAUX>(im, plane, m * (WAVE * D::VEC), g * Q, qg, lane);
+}
+
+// Kernels that take packed last strips: fused, and direct25 for FP32 (the
+// 16-bit direct25 kernel would need twice its registers for the packed band),
+// aligned images, one wave per workgroup, unrolled bands.
+template <class D, bool AL, int MODE, int WAVES, int TH>
+constexpr bool packs() {
+    return AL && WAVES == 1 && TH > 0 &&
+           (MODE == MODE_FUSED || (MODE == MODE_DIRECT25 && D::ESZ == 4));
+}
+
+// PK: the launch holds images with a packed last strip (kernels of their
+// own, so that the others carry no code for it).
+template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT, bool PK = false>
 __device__ __forceinline__ void run_tile(const ImgDev &im, int64_t lt, int wave, int lane) {
+    if constexpr (PK && packs<D, AL, MODE, WAVES, TH>()) {
+        if (im.tq > 1) {
+            run_tile_packed<D, AL, MODE, TH, SAUX>(im, lt, lane);
+            return;
+        }
+    }
     const int sg = (int)(lt % im.nsg);
     const int64_t t = lt / im.nsg;
     const int band = (int)(t % im.nb);
     const int plane = (int)(t / im.nb);
     const int strip = sg * WAVES + wave;
     if (strip >= im.ns) return;
+    run_strip_band<D, AL, MODE, TH, SAUX>(im, plane, strip, band, lane);
+}
+
+template <class D, bool AL, int MODE, int TH, int SAUX>
+__device__ __forceinline__ void run_strip_band(const ImgDev &im, int plane, int strip, int band,
+                                               int lane) {
     const int xs = strip * (WAVE * D::VEC);
     const int y0 = band * im.th;
     const int y1 = min(y0 + im.th, im.rows);
@@ -674,12 +917,21 @@ __device__ __forceinline__ int xcd_chunk_remap(int b, int n, int64_t T) {
     return (int)((x + X * (i / T)) * T + i % T);
 }
 
+// Tiles in a chunk of xcd_slabs band rows (with a packed last strip: of
+// xcd_slabs / tq band groups, at least one).
+template <bool PK>
+__device__ __forceinline__ int64_t chunk_tiles(const ImgDev &im) {
+    if (PK && im.tq > 1)
+        return (int64_t)max(1, im.xcd_slabs / im.tq) * ((int64_t)im.tq * (im.ns - 1) + 1);
+    return (int64_t)im.xcd_slabs * im.nsg;
+}
+
 // One workgroup per logical tile; grids above 2^20 workgroups loop.  In
 // launch order (xcd_slabs = 0) the resident waves sweep the image row-band by
 // row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows; with
 // xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows.  SAUX is
 // the cache policy of the output stores.
-template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT>
+template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT, bool PK = false>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -688,10 +940,9 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblock
         const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
         if ((int)blockIdx.x >= cnt) break;
         const int b = im.xcd_slabs == 1   ? xcd_remap(blockIdx.x, cnt)
-                      : im.xcd_slabs > 1 ? xcd_chunk_remap(blockIdx.x, cnt,
-                                                            (int64_t)im.xcd_slabs * im.nsg)
+                      : im.xcd_slabs > 1 ? xcd_chunk_remap(blockIdx.x, cnt, chunk_tiles<PK>(im))
                                          : (int)blockIdx.x;
-        run_tile<D, AL, MODE, WAVES, TH, SAUX>(im, base + b, wave, lane);
+        run_tile<D, AL, MODE, WAVES, TH, SAUX, PK>(im, base + b, wave, lane);
     }
 }
 
@@ -720,7 +971,10 @@ __device__ __forceinline__ int find_image(const ImgDev *__restrict__ descs, int 
     return lo;
 }
 
-template <class D, int MODE, int WAVES, int TH>
+// ANY_UNAL: the batch holds images that are not aligned, so the kernel
+// carries the element-wise path too (which needs more registers, and so
+// lowers the occupancy of the whole kernel).
+template <class D, int MODE, int WAVES, int TH, bool ANY_UNAL, bool PK>
 __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int n, int64_t total) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -755,28 +1009,28 @@ __device__ __forceinline__ void batch_body(const ImgDev *__restrict__ descs, int
         else
             while (i < n - 1 && t >= descs[i].tile_end) ++i;
         const ImgDev &im = descs[i];
-        if (im.aligned)
-            run_tile<D, true, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);
-        else
+        if (!ANY_UNAL || im.aligned)
+            run_tile<D, true, MODE, WAVES, TH, NT, PK>(im, t - im.tile_begin, wave, lane);
+        else if constexpr (ANY_UNAL)
             run_tile<D, false, MODE, WAVES, TH>(im, t - im.tile_begin, wave, lane);
     }
 }
 
-template <class D, int MODE, int WAVES, int TH>
+template <class D, int MODE, int WAVES, int TH, bool ANY_UNAL, bool PK>
 __global__ __launch_bounds__(WAVE *WAVES) void k_batch(const ImgDev *__restrict__ descs, int n,
                                                        int64_t total) {
-    batch_body<D, MODE, WAVES, TH>(descs, n, total);
+    batch_body<D, MODE, WAVES, TH, ANY_UNAL, PK>(descs, n, total);
 }
 
 // Same kernel with the descriptors in the kernel argument.  The argument is
 // read in place through the kernarg segment pointer (it is the only explicit
 // argument, so it starts at offset 0): indexing the by-value parameter itself
 // would make the compiler copy it to per-lane scratch memory.
-template <class D, int MODE, int WAVES, int TH>
+template <class D, int MODE, int WAVES, int TH, bool ANY_UNAL, bool PK>
 __global__ __launch_bounds__(WAVE *WAVES) void k_batch_args(BatchArgs) {
     typedef const __attribute__((address_space(4))) BatchArgs ConstArgs;
     ConstArgs *a = (ConstArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-    batch_body<D, MODE, WAVES, TH>((const ImgDev *)a->d, a->n, a->total);
+    batch_body<D, MODE, WAVES, TH, ANY_UNAL, PK>((const ImgDev *)a->d, a->n, a->total);
 }
 
 // ---- launchers -------------------------------------------------------------------
@@ -784,9 +1038,26 @@ template <class D, bool AL, int MODE, int WAVES, int SAUX>
 hipError_t launch_image_th_p(const ImgDev &im, int64_t nblocks, hipStream_t s) {
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     const dim3 blk(WAVE * WAVES);
+    const bool pk = im.tq > 1;
     switch (im.th) {
-    case 4: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
-    case 8: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
+    case 4:
+        if constexpr (packs<D, AL, MODE, WAVES, 4>()) {
+            if (pk) {
+                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX, true>), dim3(grid), blk, 0, s, im, nblocks);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX>), dim3(grid), blk, 0, s, im, nblocks);
+        break;
+    case 8:
+        if constexpr (packs<D, AL, MODE, WAVES, 8>()) {
+            if (pk) {
+                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX, true>), dim3(grid), blk, 0, s, im, nblocks);
+                break;
+            }
+        }
+        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX>), dim3(grid), blk, 0, s, im, nblocks);
+        break;
     default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
     }
     return hipGetLastError();
@@ -828,59 +1099,105 @@ hipError_t launch_image_t(const ImgDev &im, int mode, int waves, int64_t nblocks
                       : launch_image_m<D, false>(im, mode, waves, nblocks, s);
 }
 
-template <class D, int MODE, int WAVES>
-hipError_t launch_batch_th(const ImgDev *d, int n, int64_t total, int th, int grid, hipStream_t s) {
+// Batch kernel for the launch's flags (kBatchAnyUnaligned, kBatchAnyPacked);
+// packed-strip kernels exist for one-wave workgroups with 4- or 8-row bands.
+template <class D, int MODE, int WAVES, int TH, bool U>
+hipError_t launch_batch_k(const ImgDev *d, int n, int64_t total, bool pk, int grid, hipStream_t s) {
     const dim3 blk(WAVE * WAVES);
-    switch (th) {
-    case 4: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 4>), dim3(grid), blk, 0, s, d, n, total); break;
-    case 8: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 8>), dim3(grid), blk, 0, s, d, n, total); break;
-    default: hipLaunchKernelGGL((k_batch<D, MODE, WAVES, 0>), dim3(grid), blk, 0, s, d, n, total); break;
+    if constexpr (packs<D, true, MODE, WAVES, TH>()) {
+        if (pk) {
+            hipLaunchKernelGGL((k_batch<D, MODE, WAVES, TH, U, true>), dim3(grid), blk, 0, s, d, n, total);
+            return hipGetLastError();
+        }
     }
+    hipLaunchKernelGGL((k_batch<D, MODE, WAVES, TH, U, false>), dim3(grid), blk, 0, s, d, n, total);
     return hipGetLastError();
 }
 
-template <class D, int MODE>
-hipError_t launch_batch_w(const ImgDev *d, int n, int64_t total, int waves, int th, int grid,
-                          hipStream_t s) {
-    switch (waves) {
-    case 1: return launch_batch_th<D, MODE, 1>(d, n, total, th, grid, s);
-    case 2: return launch_batch_th<D, MODE, 2>(d, n, total, th, grid, s);
-    default: return launch_batch_th<D, MODE, 4>(d, n, total, th, grid, s);
+template <class D, int MODE, int WAVES, bool U>
+hipError_t launch_batch_th(const ImgDev *d, int n, int64_t total, int th, bool pk, int grid,
+                           hipStream_t s) {
+    switch (th) {
+    case 4: return launch_batch_k<D, MODE, WAVES, 4, U>(d, n, total, pk, grid, s);
+    case 8: return launch_batch_k<D, MODE, WAVES, 8, U>(d, n, total, pk, grid, s);
+    default: return launch_batch_k<D, MODE, WAVES, 0, U>(d, n, total, pk, grid, s);
     }
+}
+
+template <class D, int MODE, bool U>
+hipError_t launch_batch_w(const ImgDev *d, int n, int64_t total, int waves, int th, bool pk,
+                          int grid, hipStream_t s) {
+    switch (waves) {
+    case 1: return launch_batch_th<D, MODE, 1, U>(d, n, total, th, pk, grid, s);
+    case 2: return launch_batch_th<D, MODE, 2, U>(d, n, total, th, pk, grid, s);
+    default: return launch_batch_th<D, MODE, 4, U>(d, n, total, th, pk, grid, s);
+    }
+}
+
+template <class D, bool U>
+hipError_t launch_batch_m(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
+                          bool pk, int grid, hipStream_t s) {
+    return mode == MODE_DIRECT25
+               ? launch_batch_w<D, MODE_DIRECT25, U>(d, n, total, waves, th, pk, grid, s)
+               : launch_batch_w<D, MODE_FUSED, U>(d, n, total, waves, th, pk, grid, s);
 }
 
 template <class D>
 hipError_t launch_batch_t(const ImgDev *d, int n, int64_t total, int mode, int waves, int th,
-                          int grid, hipStream_t s) {
-    return mode == MODE_DIRECT25 ? launch_batch_w<D, MODE_DIRECT25>(d, n, total, waves, th, grid, s)
-                                 : launch_batch_w<D, MODE_FUSED>(d, n, total, waves, th, grid, s);
+                          int grid, int flags, hipStream_t s) {
+    const bool pk = (flags & kBatchAnyPacked) != 0;
+    return (flags & kBatchAnyUnaligned)
+               ? launch_batch_m<D, true>(d, n, total, mode, waves, th, pk, grid, s)
+               : launch_batch_m<D, false>(d, n, total, mode, waves, th, pk, grid, s);
 }
 
-template <class D, int MODE, int WAVES>
-hipError_t launch_batch_args_th(const BatchArgs &a, int th, int grid, hipStream_t s) {
+template <class D, int MODE, int WAVES, int TH, bool U>
+hipError_t launch_batch_args_k(const BatchArgs &a, bool pk, int grid, hipStream_t s) {
     const dim3 blk(WAVE * WAVES);
-    switch (th) {
-    case 4: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 4>), dim3(grid), blk, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 8>), dim3(grid), blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, 0>), dim3(grid), blk, 0, s, a); break;
+    if constexpr (packs<D, true, MODE, WAVES, TH>()) {
+        if (pk) {
+            hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, TH, U, true>), dim3(grid), blk, 0, s, a);
+            return hipGetLastError();
+        }
     }
+    hipLaunchKernelGGL((k_batch_args<D, MODE, WAVES, TH, U, false>), dim3(grid), blk, 0, s, a);
     return hipGetLastError();
 }
 
-template <class D, int MODE>
-hipError_t launch_batch_args_w(const BatchArgs &a, int waves, int th, int grid, hipStream_t s) {
-    switch (waves) {
-    case 1: return launch_batch_args_th<D, MODE, 1>(a, th, grid, s);
-    case 2: return launch_batch_args_th<D, MODE, 2>(a, th, grid, s);
-    default: return launch_batch_args_th<D, MODE, 4>(a, th, grid, s);
+template <class D, int MODE, int WAVES, bool U>
+hipError_t launch_batch_args_th(const BatchArgs &a, int th, bool pk, int grid, hipStream_t s) {
+    switch (th) {
+    case 4: return launch_batch_args_k<D, MODE, WAVES, 4, U>(a, pk, grid, s);
+    case 8: return launch_batch_args_k<D, MODE, WAVES, 8, U>(a, pk, grid, s);
+    default: return launch_batch_args_k<D, MODE, WAVES, 0, U>(a, pk, grid, s);
     }
+}
+
+template <class D, int MODE, bool U>
+hipError_t launch_batch_args_w(const BatchArgs &a, int waves, int th, bool pk, int grid,
+                               hipStream_t s) {
+    switch (waves) {
+    case 1: return launch_batch_args_th<D, MODE, 1, U>(a, th, pk, grid, s);
+    case 2: return launch_batch_args_th<D, MODE, 2, U>(a, th, pk, grid, s);
+    default: return launch_batch_args_th<D, MODE, 4, U>(a, th, pk, grid, s);
+    }
+}
+
+template <class D, bool U>
+hipError_t launch_batch_args_m(const BatchArgs &a, int mode, int waves, int th, bool pk, int grid,
+                               hipStream_t s) {
+    return mode == MODE_DIRECT25
+               ? launch_batch_args_w<D, MODE_DIRECT25, U>(a, waves, th, pk, grid, s)
+               : launch_batch_args_w<D, MODE_FUSED, U>(a, waves, th, pk, grid, s);
 }
 
 template <class D>
 hipError_t launch_batch_args_t(const BatchArgs &a, int mode, int waves, int th, int grid,
-                               hipStream_t s) {
-    return mode == MODE_DIRECT25 ? launch_batch_args_w<D, MODE_DIRECT25>(a, waves, th, grid, s)
-                                 : launch_batch_args_w<D, MODE_FUSED>(a, waves, th, grid, s);
+                               int flags, hipStream_t s) {
+    const bool pk = (flags & kBatchAnyPacked) != 0;
+    return (flags & kBatchAnyUnaligned)
+               ? launch_batch_args_m<D, true>(a, mode, waves, th, pk, grid, s)
+               : launch_batch_args_m<D, false>(a, mode, waves, th, pk, grid, s);
 }
 
 }  // namespace

@@ -9,13 +9,13 @@ hipError_t launch_image_bf16(const ImgDev &im, int mode, int waves, int64_t nblo
 }
 
 hipError_t launch_batch_bf16(const ImgDev *d_descs, int n, int64_t total_tiles, int mode,
-                          int waves, int th, int grid, hipStream_t s) {
-    return launch_batch_t<BF16>(d_descs, n, total_tiles, mode, waves, th, grid, s);
+                          int waves, int th, int grid, int flags, hipStream_t s) {
+    return launch_batch_t<BF16>(d_descs, n, total_tiles, mode, waves, th, grid, flags, s);
 }
 
 hipError_t launch_batch_args_bf16(const BatchArgs &a, int mode, int waves, int th, int grid,
-                              hipStream_t s) {
-    return launch_batch_args_t<BF16>(a, mode, waves, th, grid, s);
+                              int flags, hipStream_t s) {
+    return launch_batch_args_t<BF16>(a, mode, waves, th, grid, flags, s);
 }
 
 }  // namespace convsep5

@@ -9,13 +9,13 @@ hipError_t launch_image_f32(const ImgDev &im, int mode, int waves, int64_t nbloc
 }
 
 hipError_t launch_batch_f32(const ImgDev *d_descs, int n, int64_t total_tiles, int mode,
-                          int waves, int th, int grid, hipStream_t s) {
-    return launch_batch_t<F32>(d_descs, n, total_tiles, mode, waves, th, grid, s);
+                          int waves, int th, int grid, int flags, hipStream_t s) {
+    return launch_batch_t<F32>(d_descs, n, total_tiles, mode, waves, th, grid, flags, s);
 }
 
 hipError_t launch_batch_args_f32(const BatchArgs &a, int mode, int waves, int th, int grid,
-                              hipStream_t s) {
-    return launch_batch_args_t<F32>(a, mode, waves, th, grid, s);
+                              int flags, hipStream_t s) {
+    return launch_batch_args_t<F32>(a, mode, waves, th, grid, flags, s);
 }
 
 }  // namespace convsep5

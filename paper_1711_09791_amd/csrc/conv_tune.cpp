@@ -1,8 +1,9 @@
 // conv_tune.cpp -- the tile-shape autotuner.  It times every candidate
 // configuration on the caller's workload with HIP events and installs the
 // fastest.  All candidates compute bitwise identical results; only the
-// decomposition into tiles (rows per band, wavefronts per workgroup and the
-// persistent grid size) changes.
+// decomposition into tiles (rows per band, wavefronts per workgroup, the
+// persistent grid size, the XCD order and the packing of narrow last strips)
+// changes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,6 +15,17 @@ using namespace convsep5;
 
 namespace {
 
+// Configurations whose kernels can pack a narrow last strip are tried with
+// packing on and off; for the others the setting has no effect.
+void add(std::vector<conv_tile_cfg> &c, int th, int w, int p, int x) {
+    if (w == 1 && (th == 4 || th == 8)) {
+        c.push_back({th, w, p, x, -1});
+        c.push_back({th, w, p, x, 1});
+    } else {
+        c.push_back({th, w, p, x, 0});
+    }
+}
+
 std::vector<conv_tile_cfg> candidates(int kind) {
     std::vector<conv_tile_cfg> c;
     const int ths[] = {4, 8, 16, 32, 64};
@@ -22,7 +34,7 @@ std::vector<conv_tile_cfg> candidates(int kind) {
         const int xcd[] = {0, 1, 4, 8, 16};
         for (int x : xcd)
             for (int th : ths)
-                for (int w : waves) c.push_back({th, w, 0, x});
+                for (int w : waves) add(c, th, w, 0, x);
         return c;
     }
     const int persist[] = {0, 4, 8, 16};
@@ -30,7 +42,7 @@ std::vector<conv_tile_cfg> candidates(int kind) {
     for (int x : xcd)
         for (int th : ths)
             for (int w : waves)
-                for (int p : persist) c.push_back({th, w, p, x});
+                for (int p : persist) add(c, th, w, p, x);
     return c;
 }
 

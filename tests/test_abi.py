@@ -152,11 +152,18 @@ def test_tile_cfg_validation_and_roundtrip():
         cs.conv_set_tile_cfg(0, 1, 32, 1, 33)
     with pytest.raises(cs.ConvError):
         cs.conv_get_tile_cfg(4, 0)
-    cs.conv_set_tile_cfg(2, 1, 48, 2, 6)
+    b2 = cs.conv_get_tile_cfg(2, 1)
+    cs.conv_set_tile_cfg(2, 1, 48, 2, 6, 0, -1)
     c = cs.conv_get_tile_cfg(2, 1)
-    assert (c.rows_per_tile, c.waves_per_wg, c.persist_wgs_per_cu) == (48, 2, 6)
+    assert (c.rows_per_tile, c.waves_per_wg, c.persist_wgs_per_cu, c.pack_tail) == (48, 2, 6, -1)
+    cs.conv_set_tile_cfg(2, 1, **b2.as_dict())
+    assert cs.conv_get_tile_cfg(2, 1).as_dict() == b2.as_dict()
+    assert b2.pack_tail == 0          # default: pack when the launch is large
     with pytest.raises(cs.ConvError):
         cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 4097)   # XCD chunk out of range
+    for bad in (-2, 2):
+        with pytest.raises(cs.ConvError):
+            cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 8, bad)  # pack_tail is -1, 0 or 1
     b16 = cs.conv_get_tile_cfg(1, 0)
     cs.conv_set_tile_cfg(1, 0, 8, 1, 0, 16)
     assert cs.conv_get_tile_cfg(1, 0).xcd_slabs == 16
