@@ -12,8 +12,9 @@ Also measured and reported in the same JSON line:
   forms      the two-pass form (HBM intermediate), the direct 25-tap form and a
              device copy of the same bytes (the achievable ceiling);
   precision  the fused form with FP16 and BF16 storage (FP32 accumulation);
-  batch      64 uneven images (H, W = 8*U{30..270}) in one persistent launch,
-             eager and as a captured graph, against one launch per image;
+  batch      64 uneven images (H, W = 8*U{30..270}) in one persistent launch
+             (FP32, and the same images stored as FP16 and BF16), eager
+             (FP32 also as a captured graph), against one launch per image;
   serving    Poisson arrivals of 640x480 .. 3840x2160 frames, each with its
              own taps: p50/p99 latency of the continuous-batching server
              against the same server restricted to one image per launch, at
@@ -307,48 +308,68 @@ def bench_pyramid(torch, cs, host, k, args):
 
 
 def bench_batch(torch, cs, synth, args):
-    """64 uneven FP32 images: persistent batch launch, graph replay, per-image launches."""
+    """64 uneven images: persistent batch launch, graph replay (FP32), one
+    launch per image; FP32, then the same batch stored as FP16 and BF16."""
     shapes = synth.batch_shapes(3, 64)
-    ins = [torch.from_numpy(synth.image(100 + i, 3, h, w)).cuda() for i, (h, w) in enumerate(shapes)]
-    outs = [torch.empty_like(a) for a in ins]
-    ks = [synth.taps_random(200 + i) for i in range(64)]
     pix = sum(h * w for h, w in shapes)
-    nbytes = 24 * pix
     steps = max(20, args.steps // 4)
     warm = max(3, args.warmup // 10)
-    # arguments marshalled once, so that the timed loops measure the launches
-    L = cs.lib()
-    n = len(ins)
-    pin = (ctypes.c_void_p * n)(*[a.data_ptr() for a in ins])
-    pout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
-    kk = (ctypes.c_float * (5 * n))(*[float(v) for k in ks for v in k])
-    imgs = (cs.conv_image * n)(*[cs.image_of(a) for a in ins])
-    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    t_eager = timed(torch, lambda i: check(cs, L.conv_sep5_batch(n, pin, pout, kk, imgs, 0, hs)),
-                    steps, warm)
-    plan = cs.conv_batch_plan_create(ins, outs, ks)
-    t_graph = timed(torch, lambda i: plan.launch(), steps, warm)
-    plan.destroy()
-    one = [(ctypes.c_void_p(pin[j]), ctypes.c_void_p(pout[j]), (ctypes.c_float * 5)(*kk[5 * j:5 * j + 5]),
-            ctypes.byref(imgs[j])) for j in range(n)]
+    ks = [synth.taps_random(200 + i) for i in range(64)]
+    res = {}
+    for dt, tdt, esz in (("f32", torch.float32, 4), ("f16", torch.float16, 2),
+                         ("bf16", torch.bfloat16, 2)):
+        ins = [torch.from_numpy(synth.image(100 + i, 3, h, w)).cuda().to(tdt)
+               for i, (h, w) in enumerate(shapes)]
+        outs = [torch.empty_like(a) for a in ins]
+        nbytes = 6 * esz * pix
+        # arguments marshalled once, so that the timed loops measure the launches
+        L = cs.lib()
+        n = len(ins)
+        pin = (ctypes.c_void_p * n)(*[a.data_ptr() for a in ins])
+        pout = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        kk = (ctypes.c_float * (5 * n))(*[float(v) for k in ks for v in k])
+        imgs = (cs.conv_image * n)(*[cs.image_of(a) for a in ins])
+        hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        t_eager = timed(torch, lambda i: check(cs, L.conv_sep5_batch(n, pin, pout, kk, imgs, 0, hs)),
+                        steps, warm)
+        t_graph = None
+        if dt == "f32":
+            plan = cs.conv_batch_plan_create(ins, outs, ks)
+            t_graph = timed(torch, lambda i: plan.launch(), steps, warm)
+            plan.destroy()
+        one = [(ctypes.c_void_p(pin[j]), ctypes.c_void_p(pout[j]),
+                (ctypes.c_float * 5)(*kk[5 * j:5 * j + 5]), ctypes.byref(imgs[j])) for j in range(n)]
 
-    def lone(i):
-        for a, o, k, im in one:
-            check(cs, L.conv_sep5_1pass(a, o, k, im, 0, hs))
+        def lone(i):
+            for a, o, k, im in one:
+                check(cs, L.conv_sep5_1pass(a, o, k, im, 0, hs))
 
-    t_lone = timed(torch, lone, steps, warm)
-    cfg = cs.conv_get_tile_cfg(0, 1).as_dict()
-    ms_e, ms_g, ms_l = t_eager / steps, t_graph / steps, t_lone / steps
-    return {
-        "images": 64, "mpix": pix / 1e6, "alg_bytes": nbytes, "tile_cfg": cfg,
-        "eager_ms": ms_e, "graph_ms": ms_g, "per_image_launches_ms": ms_l,
-        "eager_mpix_per_s": pix / (ms_e * 1e-3) / 1e6,
-        "graph_mpix_per_s": pix / (ms_g * 1e-3) / 1e6,
-        "per_image_mpix_per_s": pix / (ms_l * 1e-3) / 1e6,
-        "graph_alg_GBps": nbytes / (ms_g * 1e-3) / 1e9,
-        "graph_frac_of_hbm_peak": nbytes / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "speedup_vs_per_image": ms_l / ms_g,
-    }
+        t_lone = timed(torch, lone, steps, warm)
+        ms_e, ms_l = t_eager / steps, t_lone / steps
+        r = {
+            "images": 64, "mpix": pix / 1e6, "alg_bytes": nbytes,
+            "tile_cfg": cs.conv_get_tile_cfg({"f32": 0, "f16": 1, "bf16": 2}[dt], 1).as_dict(),
+            "eager_ms": ms_e, "per_image_launches_ms": ms_l,
+            "eager_mpix_per_s": pix / (ms_e * 1e-3) / 1e6,
+            "per_image_mpix_per_s": pix / (ms_l * 1e-3) / 1e6,
+            "eager_alg_GBps": nbytes / (ms_e * 1e-3) / 1e9,
+            "eager_frac_of_hbm_peak": nbytes / (ms_e * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "speedup_vs_per_image": ms_l / ms_e,
+        }
+        if t_graph is not None:
+            ms_g = t_graph / steps
+            r.update({
+                "graph_ms": ms_g,
+                "graph_mpix_per_s": pix / (ms_g * 1e-3) / 1e6,
+                "graph_alg_GBps": nbytes / (ms_g * 1e-3) / 1e9,
+                "graph_frac_of_hbm_peak": nbytes / (ms_g * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "speedup_vs_per_image": ms_l / ms_g,
+            })
+        res[dt] = r
+        del ins, outs
+    out = dict(res["f32"])
+    out["16bit"] = {"f16": res["f16"], "bf16": res["bf16"]}
+    return out
 
 
 def bench_serving(torch, cs, synth, args, sizes=None):
