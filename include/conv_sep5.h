@@ -282,6 +282,9 @@ conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *
  * installs the fastest with conv_set_tile_cfg and returns it in *best, with
  * its median time per launch in *best_ms.  kind 0 tunes on image 0 alone
  * (fused 1pass), kind 1 on the whole batch.  Synchronises `stream`.
+ * The launches reuse the same buffers, so a workload whose input and output
+ * fit the GPU's 256 MB last-level cache is timed with a warm cache (where
+ * other tile orders win than for images streamed from HBM).
  */
 conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_in,
                       void *const *d_out, const float *k,
