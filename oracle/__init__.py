@@ -15,6 +15,9 @@ per-plane driver of Section 5.3):
 
 ``conv5(A, k)``            single-pass (25-term) form in FP64.
 ``conv5_twopass(A, k)``    separable two-pass form in FP64.
+``conv5_twopass_t(A, k, t)``  the two-pass form with its auxiliary array (the
+                           intermediate) rounded once to t = "f16" or "bf16"
+                           (RNE) between the passes; "f32" is conv5_twopass.
 ``conv_direct_n(A, K)``    Eq. 1 at odd width n with a full n x n kernel K.
 ``conv_sep_n(A, k)``       the same with K = k k^T (products in FP64, exact).
 ``pyr_down(A, k)``         one pyramid level: conv5, then every second row and
@@ -68,6 +71,8 @@ def _load():
     lib.oracle_conv5_direct.restype = None
     lib.oracle_conv5_twopass.argtypes = [dp, dp, dp, dp, i64, i64, i64]
     lib.oracle_conv5_twopass.restype = None
+    lib.oracle_conv5_twopass_q.argtypes = [dp, dp, dp, dp, i64, i64, i64, ctypes.c_int]
+    lib.oracle_conv5_twopass_q.restype = None
     lib.oracle_conv_direct_n.argtypes = [dp, dp, dp, ctypes.c_int, i64, i64, i64, ctypes.c_int]
     lib.oracle_conv_direct_n.restype = None
     lib.oracle_decode_f32.argtypes = [fp, dp, i64]
@@ -132,6 +137,26 @@ def conv5_twopass(A, k) -> np.ndarray:
     _load().oracle_conv5_twopass(_ptr(A, ctypes.c_double), _ptr(B, ctypes.c_double),
                                  _ptr(aux, ctypes.c_double), _ptr(k, ctypes.c_double),
                                  P, R, C)
+    return B[0] if squeeze else B
+
+
+def conv5_twopass_t(A, k, tdtype: str) -> np.ndarray:
+    """Two-pass form with a 16-bit intermediate: exact row pass on every row,
+    each intermediate value rounded once (RNE) to tdtype ("f16" or "bf16"),
+    exact column pass over the rounded values; border 0.  "f32" gives
+    conv5_twopass (the FP64 intermediate, unrounded)."""
+    if tdtype == "f32":
+        return conv5_twopass(A, k)
+    fmt = {"f16": 1, "bf16": 2}[tdtype]
+    squeeze = np.asarray(A).ndim == 2
+    A = _as_planes(A)
+    k = _taps(k)
+    B = np.empty_like(A)
+    P, R, C = A.shape
+    aux = np.empty((max(R * C, 1),), dtype=np.float64)
+    _load().oracle_conv5_twopass_q(_ptr(A, ctypes.c_double), _ptr(B, ctypes.c_double),
+                                   _ptr(aux, ctypes.c_double), _ptr(k, ctypes.c_double),
+                                   P, R, C, fmt)
     return B[0] if squeeze else B
 
 

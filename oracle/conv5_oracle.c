@@ -18,6 +18,9 @@
  *   - Planes are independent (Section 5.3, the per-plane driver loop).
  *   - The same Eq. 1 at any odd width n with any n x n kernel, separable or
  *     not (oracle_conv_direct_n), for the width-n kernels.
+ *   - The two-pass form with its auxiliary array rounded to a 16-bit format
+ *     (oracle_conv5_twopass_q), a reduced-precision variant with its own
+ *     definition.
  *
  * All arithmetic is IEEE binary64.  The 16-bit helpers decode half and bfloat16
  * storage exactly and round binary64 results to those formats with
@@ -274,6 +277,53 @@ void oracle_round_bf16(const double *src, uint16_t *dst, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i)
         dst[i] = double_to_bf16_bits(src[i]);
+}
+
+/*
+ * Two-pass form with a 16-bit auxiliary array.  The paper's auxiliary array
+ * (the intermediate of the two-pass form, Section 7) holds float values; this
+ * variant keeps it in a narrower format to halve its memory traffic, which
+ * changes the arithmetic, so it has its own definition: the horizontal pass is
+ * computed exactly as in oracle_conv5_twopass (binary64, every row, columns
+ * 2..cols-3, zero elsewhere); each auxiliary value is then rounded once to the
+ * 16-bit format with round-to-nearest-even (tfmt 1: IEEE binary16, 2:
+ * bfloat16); the vertical pass reads the rounded values, exactly, in binary64.
+ */
+void oracle_conv5_twopass_q(const double *A, double *B, double *aux,
+                            const double *k, int64_t planes, int64_t rows,
+                            int64_t cols, int tfmt)
+{
+    const int64_t n_plane = rows * cols;
+    if (n_plane == 0 || planes == 0)
+        return;
+    memset(B, 0, sizeof(double) * (size_t)(planes * n_plane));
+    if (rows < 2 * R5 + 1 || cols < 2 * R5 + 1)
+        return;
+    for (int64_t p = 0; p < planes; ++p) {
+        const double *in = A + p * n_plane;
+        double *out = B + p * n_plane;
+        memset(aux, 0, sizeof(double) * (size_t)n_plane);
+        /* horizontal pass on every row */
+        for (int64_t i = 0; i < rows; ++i)
+            for (int64_t j = R5; j < cols - R5; ++j) {
+                double h = 0.0;
+                for (int d = -R5; d <= R5; ++d)
+                    h += in[i * cols + j + d] * k[d + R5];
+                aux[i * cols + j] = h;
+            }
+        /* the auxiliary array in the 16-bit format */
+        for (int64_t e = 0; e < n_plane; ++e)
+            aux[e] = tfmt == 1 ? half_bits_to_double(double_to_half_bits(aux[e]))
+                               : bf16_bits_to_double(double_to_bf16_bits(aux[e]));
+        /* vertical pass over the rounded values */
+        for (int64_t i = R5; i < rows - R5; ++i)
+            for (int64_t j = R5; j < cols - R5; ++j) {
+                double v = 0.0;
+                for (int d = -R5; d <= R5; ++d)
+                    v += aux[(i + d) * cols + j] * k[d + R5];
+                out[i * cols + j] = v;
+            }
+    }
 }
 
 /* Number of OpenMP threads a parallel region of the oracle would use. */

@@ -9,10 +9,14 @@ Sources of truth used here, none of which is the oracle:
   which compute Eq. 1 as a correlation on the 'valid' region;
 * brute force: Eq. 1 written with an explicit K[i][j] = k_i k_j matrix in
   pure Python on tiny images;
-* closed forms: delta impulse, constant image, linear ramp, exact rationals.
+* closed forms: delta impulse, constant image, linear ramp, exact rationals;
+* for the two-pass form with a 16-bit intermediate: an independent rounding
+  (Python's round-half-even on the scaled value) in a brute-force loop, exact
+  dyadic cases and the closed-form error bound of one rounding per value.
 """
 from __future__ import annotations
 
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -430,3 +434,127 @@ def nearest_even_bf16(x: float) -> int:
     best = min(order, key=lambda i: (abs(Fraction(float(v[i])) - fx),
                                      int(bits[cand[i]]) & 1))
     return int(bits[cand[best]])
+
+
+# ---- two-pass form with a 16-bit intermediate ----------------------------------
+
+T16_FORMATS = {"f16": (10, -14), "bf16": (7, -126)}  # fraction bits, min normal exponent
+
+
+def _rne_py(x: float, mbits: int, emin: int) -> float:
+    """RNE of a finite double to a binary format with `mbits` fraction bits,
+    written independently of the oracle: the quantum at x's exponent (fixed
+    below the smallest normal), then Python's round(), which sends halves to
+    the even integer."""
+    if x == 0.0:
+        return 0.0
+    _, e = math.frexp(abs(x))          # |x| = m 2^e, m in [0.5, 1)
+    q = math.ldexp(1.0, max(e - 1, emin) - mbits)
+    return math.copysign(round(abs(x) / q) * q, x)
+
+
+def _brute_t16(a2d, k, mbits, emin):
+    """Loops in the oracle's order: row pass on every row (taps left to right,
+    from 0.0), each value rounded, column pass top to bottom."""
+    R, C = a2d.shape
+    out = np.zeros((R, C))
+    if R < 5 or C < 5:
+        return out
+    T = np.zeros((R, C))
+    for y in range(R):
+        for x in range(2, C - 2):
+            t = 0.0
+            for b in range(5):
+                t += float(a2d[y, x + b - 2]) * float(k[b])
+            T[y, x] = _rne_py(t, mbits, emin)
+    for y in range(2, R - 2):
+        for x in range(2, C - 2):
+            s = 0.0
+            for a in range(5):
+                s += float(T[y + a - 2, x]) * float(k[a])
+            out[y, x] = s
+    return out
+
+
+def pin_t16_bruteforce_tiny(conv_t) -> bool:
+    """Same operations in the same order as the brute force: equal exactly,
+    for both formats, signed and unsigned data, values down to the binary16
+    subnormal range, all sizes 1..9 (below 5: zeros)."""
+    rng = np.random.default_rng(77)
+    for fmt, (mb, em) in T16_FORMATS.items():
+        for _ in range(24):
+            R, C = (int(v) for v in rng.integers(1, 10, size=2))
+            scale = float(rng.choice([1.0, 1e-6, 300.0]))
+            A = (rng.random((2, R, C)) - float(rng.choice([0.0, 0.5]))) * scale
+            k = rng.random(5) - float(rng.choice([0.0, 0.3]))
+            got = conv_t(A, k, fmt)
+            for p in range(2):
+                if not np.array_equal(got[p], _brute_t16(A[p], k, mb, em)):
+                    return False
+    return True
+
+
+def pin_t16_exact_dyadic(conv_t) -> bool:
+    """Pixels 0..3 with taps [1,4,6,4,1]/16: every intermediate is an integer
+    over 16 below 4, exact in both formats, so the result is Eq. 1 exactly."""
+    rng = np.random.default_rng(78)
+    A = rng.integers(0, 4, size=(3, 23, 31)).astype(np.float64)
+    k = np.array([1, 4, 6, 4, 1]) / 16.0
+    ref = _eq1(A, k)
+    return all(np.array_equal(conv_t(A, k, f), ref) for f in T16_FORMATS)
+
+
+def _eq1(A, k):
+    """Eq. 1 with K = k k^T on the interior, 25 shifted products in FP64."""
+    P, R, C = A.shape
+    B = np.zeros_like(A)
+    for a in range(5):
+        for b in range(5):
+            B[:, 2:R - 2, 2:C - 2] += k[a] * k[b] * A[:, a:R - 4 + a, b:C - 4 + b]
+    return B
+
+
+def pin_t16_error_bound(conv_t) -> bool:
+    """Against Eq. 1 in FP64: each intermediate carries a relative error of at
+    most 2^-(mbits+1), so |B_t - B| <= 2^-(mbits+1) sum_a |k_a| |T_a| (+ FP64
+    noise), and random data does show a nonzero difference."""
+    rng = np.random.default_rng(79)
+    A = rng.random((2, 40, 37))
+    k = rng.random(5)
+    k /= k.sum()
+    P, R, C = A.shape
+    T = np.zeros_like(A)
+    for b in range(5):
+        T[:, :, 2:C - 2] += k[b] * A[:, :, b:C - 4 + b]
+    mag = np.zeros_like(A)
+    for a in range(5):
+        mag[:, 2:R - 2, :] += abs(k[a]) * np.abs(T[:, a:R - 4 + a, :])
+    mag[:, :, :2] = 0
+    mag[:, :, C - 2:] = 0
+    ref = _eq1(A, k)
+    for f, (mb, _) in T16_FORMATS.items():
+        d = np.abs(conv_t(A, k, f) - ref)
+        if not np.all(d <= 2.0 ** -(mb + 1) * mag * (1 + 1e-12) + 1e-15):
+            return False
+        if not np.any(d > 0):
+            return False
+    return True
+
+
+T16_PINS = {
+    "t16_bruteforce_tiny": pin_t16_bruteforce_tiny,
+    "t16_exact_dyadic": pin_t16_exact_dyadic,
+    "t16_error_bound": pin_t16_error_bound,
+}
+
+
+def failing_t16_pins(conv_t) -> list[str]:
+    bad = []
+    for name, pin in T16_PINS.items():
+        try:
+            ok = pin(conv_t)
+        except Exception:
+            ok = False
+        if not ok:
+            bad.append(name)
+    return bad

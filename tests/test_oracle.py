@@ -68,6 +68,77 @@ def test_direct_n_rejects_even_width():
         oracle.conv_direct_n(np.zeros((1, 8, 8)), np.zeros((4, 4)))
 
 
+@pytest.mark.parametrize("name", sorted(pins.T16_PINS))
+def test_twopass_t16_pins(name):
+    assert pins.T16_PINS[name](oracle.conv5_twopass_t), name
+
+
+def test_twopass_t_f32_is_twopass():
+    rng = np.random.default_rng(37)
+    A = rng.random((2, 19, 23))
+    k = rng.random(5)
+    assert np.array_equal(oracle.conv5_twopass_t(A, k, "f32"), oracle.conv5_twopass(A, k))
+
+
+# plausible mistakes in the 16-bit intermediate, written around the FP64 forms:
+# no rounding at all, the other 16-bit format, rounding only the rows the
+# column pass writes, and truncation instead of round-to-nearest-even
+def _t16_from(T_fn):
+    """Row pass, T_fn on the intermediate, column pass, in the oracle's order
+    of operations (so the right T_fn reproduces it exactly)."""
+    def conv_t(A, k, f):
+        A = np.asarray(A, dtype=np.float64)
+        P, R, C = A.shape
+        B = np.zeros_like(A)
+        if R < 5 or C < 5:
+            return B
+        T = np.zeros_like(A)
+        for b in range(5):
+            T[:, :, 2:C - 2] = T[:, :, 2:C - 2] + A[:, :, b:C - 4 + b] * k[b]
+        T = T_fn(T, f)
+        for a in range(5):
+            B[:, 2:R - 2, 2:C - 2] = B[:, 2:R - 2, 2:C - 2] + T[:, a:R - 4 + a, 2:C - 2] * k[a]
+        return B
+    return conv_t
+
+
+def _other(f):
+    return "bf16" if f == "f16" else "f16"
+
+
+def _rows_only(T, f):
+    out = T.copy()
+    out[:, 2:-2] = oracle.decode(oracle.round_to(T[:, 2:-2], f), f)
+    return out
+
+
+def _truncate(T, f):
+    mb, emin = pins.T16_FORMATS[f]
+    _, e = np.frexp(T)
+    q = np.ldexp(1.0, np.maximum(e - 1, emin) - mb)
+    return np.trunc(T / q) * q
+
+
+T16_MUTANTS = {
+    "no_rounding": _t16_from(lambda T, f: T),
+    "other_format": _t16_from(lambda T, f: oracle.decode(oracle.round_to(T, _other(f)), _other(f))),
+    "interior_rows_only": _t16_from(_rows_only),
+    "truncated": _t16_from(_truncate),
+}
+
+
+@pytest.mark.parametrize("name", sorted(T16_MUTANTS))
+def test_t16_pins_reject_mutant(name):
+    assert pins.failing_t16_pins(T16_MUTANTS[name]), name
+
+
+def test_t16_reference_form_passes():
+    """The mutants' scaffold with the right rounding passes every pin, so the
+    mutants fail for their mistake, not for the scaffold."""
+    good = _t16_from(lambda T, f: oracle.decode(oracle.round_to(T, f), f))
+    assert pins.failing_t16_pins(good) == []
+
+
 @pytest.mark.parametrize("name", sorted(pins.PYR_PINS))
 def test_pyr_pins(name):
     assert pins.PYR_PINS[name](oracle.pyr_down), name

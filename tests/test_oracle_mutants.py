@@ -169,3 +169,53 @@ def test_n_pins_reject_mutant(tmp_path, name, old, new):
 def test_n_unmutated_copy_passes(tmp_path):
     lib = _build_mutant(tmp_path, "identity_n", "#define R5 2", "#define R5 2")
     assert pins.failing_n_pins(_wrap_n(lib)) == []
+
+
+# Mistakes in the two-pass form with a 16-bit intermediate (C code).
+Q_MUTANTS = [
+    ("q_not_rounded",
+     "for (int64_t e = 0; e < n_plane; ++e)",
+     "for (int64_t e = 0; e < 0; ++e)"),
+    ("q_formats_swapped",
+     "aux[e] = tfmt == 1 ? half_bits_to_double",
+     "aux[e] = tfmt == 2 ? half_bits_to_double"),
+    ("q_interior_rows_rounded_only",
+     "for (int64_t e = 0; e < n_plane; ++e)",
+     "for (int64_t e = R5 * cols; e < n_plane - R5 * cols; ++e)"),
+    ("q_row_pass_interior_only",
+     "for (int64_t i = 0; i < rows; ++i)\n            for (int64_t j = R5; j < cols - R5; ++j) {\n                double h",
+     "for (int64_t i = R5; i < rows - R5; ++i)\n            for (int64_t j = R5; j < cols - R5; ++j) {\n                double h"),
+    ("q_vertical_tap_flipped",
+     "v += aux[(i + d) * cols + j] * k[d + R5];",
+     "v += aux[(i + d) * cols + j] * k[R5 - d];"),
+]
+
+
+def _wrap_q(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    f = lib.oracle_conv5_twopass_q
+    f.argtypes = [dp, dp, dp, dp, i64, i64, i64, ctypes.c_int]
+
+    def conv_t(A, k, fmt):
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64))
+        B = np.empty_like(A)
+        P, R, C = A.shape
+        aux = np.empty((max(R * C, 1),))
+        p = lambda a: a.ctypes.data_as(dp)  # noqa: E731
+        f(p(A), p(B), p(aux), p(k), P, R, C, {"f16": 1, "bf16": 2}[fmt])
+        return B
+
+    return conv_t
+
+
+@pytest.mark.parametrize("name,old,new", Q_MUTANTS, ids=[m[0] for m in Q_MUTANTS])
+def test_t16_pins_reject_c_mutant(tmp_path, name, old, new):
+    lib = _build_mutant(tmp_path, name, old, new)
+    assert pins.failing_t16_pins(_wrap_q(lib)), f"mutant {name} passed every pin"
+
+
+def test_t16_unmutated_copy_passes(tmp_path):
+    lib = _build_mutant(tmp_path, "identity_q", "#define R5 2", "#define R5 2")
+    assert pins.failing_t16_pins(_wrap_q(lib)) == []
