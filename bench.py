@@ -9,8 +9,9 @@ its MPix/s.  Inputs are resident in HBM; timed launches rotate over several
 input/output buffer sets so the working set exceeds the 256 MB Infinity Cache.
 
 Also measured and reported in the same JSON line:
-  forms      the two-pass form (HBM intermediate), the direct 25-tap form and a
-             device copy of the same bytes (the achievable ceiling);
+  forms      the two-pass form (HBM intermediate), the two-pass form with a
+             16-bit intermediate, the direct 25-tap form and a device copy of
+             the same bytes (the achievable ceiling);
   precision  the fused form with FP16 and BF16 storage (FP32 accumulation);
   batch      64 uneven images (H, W = 8*U{30..270}) in one persistent launch
              (FP32, and the same images stored as FP16 and BF16), eager
@@ -62,7 +63,8 @@ def parse():
     # (~25 ms) of this kernel; 1000 warm-up launches reach the steady state.
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--sets", type=int, default=3, help="rotating buffer sets")
-    ap.add_argument("--forms", default="fused,2pass,direct25,copy,1pass_copyback,2pass_inplace")
+    ap.add_argument("--forms", default="fused,2pass,direct25,copy,1pass_copyback,2pass_inplace,"
+                                       "2pass_t16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, widths, batch and serving measurements")
@@ -143,7 +145,9 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
     S = max(1, args.sets)
     ins = [base] + [base.clone() for _ in range(S - 1)]
     outs = [torch.empty_like(base) for _ in range(S)]
-    tmp = torch.empty(P * R * C, device=dev) if ("2pass" in forms or "2pass_inplace" in forms) else None
+    tmp = torch.empty(P * R * C, device=dev) if any(f.startswith("2pass") for f in forms) else None
+    # the 16-bit intermediate: FP16 for FP32 and FP16 images, BF16 for BF16 images
+    t16 = cs.CONV_BF16 if base.dtype == torch.bfloat16 else cs.CONV_F16
     for o in outs:  # the in-place forms work on the output buffers
         o.copy_(base)
     L = cs.lib()
@@ -161,11 +165,13 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
         "fused": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 0, hs)),
         "direct25": lambda i: check(cs, L.conv_sep5_1pass(pin[i % S], pout[i % S], kk, pimg, 1, hs)),
         "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, pimg, hs)),
+        "2pass_t16": lambda i: check(cs, L.conv_sep5_2pass_ex(pin[i % S], pout[i % S], ptmp, kk, pimg,
+                                                              t16, hs)),
         "copy": lambda i: outs[i % S].copy_(ins[i % S]),
     }
     alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz,
-                 "1pass_copyback": 4 * esz, "2pass_inplace": 2 * esz + 8}
-    launches = {"2pass": 2, "2pass_inplace": 2, "1pass_copyback": 2}
+                 "1pass_copyback": 4 * esz, "2pass_inplace": 2 * esz + 8, "2pass_t16": 2 * esz + 4}
+    launches = {"2pass": 2, "2pass_inplace": 2, "1pass_copyback": 2, "2pass_t16": 2}
     res = {}
     for name in forms:
         total = timed(torch, steps_fn[name], args.steps, args.warmup)
@@ -518,7 +524,8 @@ def main():
     if "precision" in want:
         prec = {}
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
-            r, _ = bench_image(torch, cs, host, k, args, dtype=dt, forms=("fused", "direct25"))
+            r, _ = bench_image(torch, cs, host, k, args, dtype=dt,
+                               forms=("fused", "direct25", "2pass", "2pass_t16"))
             prec[name] = r
         extras["precision"] = prec
         progress("precision done")

@@ -122,6 +122,31 @@ conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp,
                             hipStream_t stream);
 
 /*
+ * Two-pass form with the intermediate stored as tmp_dtype.  The paper's
+ * auxiliary array (Section 7) is float, which CONV_F32 gives (identical to
+ * conv_sep5_2pass).  CONV_F16 / CONV_BF16 keep it in 16 bits: each row-filter
+ * value is computed in FP32 as in the FP32 form and rounded once to the
+ * 16-bit format (round to nearest even) before the column pass reads it.
+ * That halves the intermediate's bytes (2 + 2 instead of 4 + 4 per
+ * plane-pixel) but adds one rounding per intermediate value: the result is
+ * not bitwise equal to the FP32 form.  Its definition is the two-pass sum with
+ * each intermediate rounded once; the deviation of one FP32 row chain near a
+ * 16-bit rounding midpoint can move that intermediate by one 16-bit unit.
+ *   d_in, d_out  as conv_sep5_2pass (d_out == d_in allowed)
+ *   d_tmp        workspace of planes*rows*cols values of tmp_dtype, dense
+ *                [plane][row][col]; must not overlap d_in or d_out; NULL:
+ *                stream-ordered library memory
+ *   k            5 FP32 taps (host array)
+ *   tmp_dtype    CONV_F32, CONV_F16 or CONV_BF16; pixel-interleaved images
+ *                (plane_stride 1) take CONV_F32 only (else CONV_EINVAL)
+ * Launches run with one wave per workgroup and the configured rows per tile
+ * and XCD order.
+ */
+conv_status conv_sep5_2pass_ex(const void *d_in, void *d_out, void *d_tmp,
+                               const float k[5], const conv_image *img,
+                               int32_t tmp_dtype, hipStream_t stream);
+
+/*
  * Single-pass form (Section 5.1 and Section 7, "single-pass without
  * copy-back": the result is written once to a separate output).  One kernel;
  * mode CONV_1PASS_FUSED keeps the row-filtered rows in registers, mode

@@ -81,7 +81,7 @@ class ConvError(RuntimeError):
 _lib = None
 
 EXPORTS = (
-    "conv_sep5_2pass", "conv_sep5_1pass", "conv_sep5_batch",
+    "conv_sep5_2pass", "conv_sep5_2pass_ex", "conv_sep5_1pass", "conv_sep5_batch",
     "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
     "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct", "conv_pyr_down",
     "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_tune",
@@ -106,6 +106,7 @@ def lib():
     cfgp = ctypes.POINTER(conv_tile_cfg)
     sig = {
         "conv_sep5_2pass": [vp, vp, vp, fp, imgp, vp],
+        "conv_sep5_2pass_ex": [vp, vp, vp, fp, imgp, i32, vp],
         "conv_sep5_1pass": [vp, vp, fp, imgp, ctypes.c_int, vp],
         "conv_sep5_batch": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, ctypes.c_int, vp],
         "conv_batch_plan_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp,
@@ -293,6 +294,17 @@ def conv_sep5_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, s
         img = image_of(d_in)
     return _check(lib().conv_sep5_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
                                         ctypes.byref(img), _stream(stream)))
+
+
+def conv_sep5_2pass_ex(d_in, d_out, k, tmp_dtype: int, d_tmp=None,
+                       img: conv_image | None = None, stream=None):
+    """Two-pass form with the intermediate stored as tmp_dtype (CONV_F32,
+    CONV_F16 or CONV_BF16); d_tmp holds planes*rows*cols values of it."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    return _check(lib().conv_sep5_2pass_ex(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
+                                           ctypes.byref(img), int(tmp_dtype), _stream(stream)))
 
 
 def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,

@@ -530,44 +530,69 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     return CONV_OK;
 }
 
-conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp, const float k[5],
-                            const conv_image *img, hipStream_t stream) {
+// The two-pass form with its intermediate in tmp_dtype (CONV_F32: the FP32
+// form; CONV_F16 / CONV_BF16: the 16-bit intermediate, one wave per workgroup).
+static conv_status twopass(const void *d_in, void *d_out, void *d_tmp, const float k[5],
+                           const conv_image *img, int32_t tmp_dtype, hipStream_t stream) {
     clear_error();
     Layout L;
     conv_status st = check_image(img, &L);
     if (st != CONV_OK) return st;
     if (!k) return set_error(CONV_EINVAL, "taps pointer is NULL");
+    if (tmp_dtype != CONV_F32 && tmp_dtype != CONV_F16 && tmp_dtype != CONV_BF16)
+        return set_error(CONV_EINVAL, "tmp_dtype %d is not CONV_F32, CONV_F16 or CONV_BF16",
+                         tmp_dtype);
+    if (L.hwc && tmp_dtype != CONV_F32)
+        return set_error(CONV_EINVAL,
+                         "pixel-interleaved (plane_stride 1) images take an FP32 intermediate only");
     if (L.empty) return CONV_OK;
     if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
     if (d_in != (const void *)d_out && overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
         return set_error(CONV_EALIAS, "input and output partially overlap");
-    const int64_t tmp_bytes = (int64_t)img->planes * img->rows * img->cols * 4;
+    const int64_t tmp_bytes =
+        (int64_t)img->planes * img->rows * img->cols * (tmp_dtype == CONV_F32 ? 4 : 2);
     if (d_tmp && (overlaps(d_tmp, tmp_bytes, d_in, L.extent_bytes) ||
                   overlaps(d_tmp, tmp_bytes, d_out, L.extent_bytes)))
         return set_error(CONV_EALIAS, "workspace overlaps the input or output");
-    float *tmp = d_tmp;
+    void *tmp = d_tmp;
     hipError_t e;
     if (!tmp) {
-        e = hipMallocAsync((void **)&tmp, (size_t)tmp_bytes, stream);
+        e = hipMallocAsync(&tmp, (size_t)tmp_bytes, stream);
         if (e != hipSuccess)
             return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)tmp_bytes,
                              hipGetErrorString(e));
     }
-    const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    int row_mode = MODE_ROWPASS, col_mode = MODE_COLPASS;
+    if (tmp_dtype != CONV_F32) {
+        cfg.waves_per_wg = 1;
+        row_mode = tmp_dtype == CONV_F16 ? MODE_ROWPASS_F16T : MODE_ROWPASS_BF16T;
+        col_mode = tmp_dtype == CONV_F16 ? MODE_COLPASS_F16T : MODE_COLPASS_BF16T;
+    }
     ImgDev d;
     if (L.hwc) {
-        const int64_t nblocks = fill_desc_hwc(&d, d_in, d_out, tmp, img, L, k);
+        const int64_t nblocks = fill_desc_hwc(&d, d_in, d_out, (float *)tmp, img, L, k);
         e = launch_hwc(d, img->dtype, MODE_ROWPASS, nblocks, stream);
         if (e == hipSuccess) e = launch_hwc(d, img->dtype, MODE_COLPASS, nblocks, stream);
     } else {
-        const int64_t nblocks = fill_desc(&d, d_in, d_out, tmp, img, L, k, cfg);
-        e = launch_image(d, img->dtype, MODE_ROWPASS, cfg.waves_per_wg, nblocks, stream);
+        const int64_t nblocks = fill_desc(&d, d_in, d_out, (float *)tmp, img, L, k, cfg);
+        e = launch_image(d, img->dtype, row_mode, cfg.waves_per_wg, nblocks, stream);
         if (e == hipSuccess)
-            e = launch_image(d, img->dtype, MODE_COLPASS, cfg.waves_per_wg, nblocks, stream);
+            e = launch_image(d, img->dtype, col_mode, cfg.waves_per_wg, nblocks, stream);
     }
     if (!d_tmp) (void)hipFreeAsync(tmp, stream);
     if (e != hipSuccess) return hip_error(e, "2pass kernel launch");
     return CONV_OK;
+}
+
+conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp, const float k[5],
+                            const conv_image *img, hipStream_t stream) {
+    return twopass(d_in, d_out, d_tmp, k, img, CONV_F32, stream);
+}
+
+conv_status conv_sep5_2pass_ex(const void *d_in, void *d_out, void *d_tmp, const float k[5],
+                               const conv_image *img, int32_t tmp_dtype, hipStream_t stream) {
+    return twopass(d_in, d_out, d_tmp, k, img, tmp_dtype, stream);
 }
 
 conv_status conv_sep5_batch(int32_t n, const void *const *d_in, void *const *d_out,

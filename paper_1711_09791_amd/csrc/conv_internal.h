@@ -12,7 +12,12 @@ enum Mode : int {
     MODE_DIRECT25 = 1,  // 25 multiply-adds per pixel (paper's single pass)
     MODE_ROWPASS = 2,   // two-pass, first kernel: input -> FP32 intermediate
     MODE_COLPASS = 3,   // two-pass, second kernel: FP32 intermediate -> output
-    MODE_COPY = 4       // copy-back of the single-pass result (in -> out, same layout)
+    MODE_COPY = 4,      // copy-back of the single-pass result (in -> out, same layout)
+    // two-pass with the intermediate stored in 16 bits (FP16 or BF16, RNE)
+    MODE_ROWPASS_F16T = 5,
+    MODE_COLPASS_F16T = 6,
+    MODE_ROWPASS_BF16T = 7,
+    MODE_COLPASS_BF16T = 8
 };
 
 // Taps as the kernels read them: k for the separable forms, K = fl32(k_a k_b)
@@ -28,7 +33,8 @@ struct Taps {
 struct ImgDev {
     const void *in;
     void *out;
-    float *tmp;           // two-pass FP32 intermediate, dense [plane][row][col]
+    float *tmp;           // two-pass intermediate, dense [plane][row][col] (FP32, or
+                          // 16-bit values for the *_F16T / *_BF16T modes)
     int64_t pitch;
     int64_t pstride;
     int32_t planes, rows, cols;

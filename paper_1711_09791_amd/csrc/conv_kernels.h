@@ -58,6 +58,19 @@ struct F32 { static constexpr int ESZ = 4, VEC = 4; };
 struct F16 { static constexpr int ESZ = 2, VEC = 8; };
 struct BF16 { static constexpr int ESZ = 2, VEC = 8; };
 
+// The two-pass kernels and the storage type of their intermediate.
+constexpr bool is_rowpass(int m) {
+    return m == MODE_ROWPASS || m == MODE_ROWPASS_F16T || m == MODE_ROWPASS_BF16T;
+}
+constexpr bool is_colpass(int m) {
+    return m == MODE_COLPASS || m == MODE_COLPASS_F16T || m == MODE_COLPASS_BF16T;
+}
+template <int MODE> struct TmpOf { using T = F32; };
+template <> struct TmpOf<MODE_ROWPASS_F16T> { using T = F16; };
+template <> struct TmpOf<MODE_COLPASS_F16T> { using T = F16; };
+template <> struct TmpOf<MODE_ROWPASS_BF16T> { using T = BF16; };
+template <> struct TmpOf<MODE_COLPASS_BF16T> { using T = BF16; };
+
 // ---- storage conversions -------------------------------------------------
 __device__ __forceinline__ float dec(F32, uint32_t b) { return __uint_as_float(b); }
 __device__ __forceinline__ float dec(F16, uint32_t b) {
@@ -212,6 +225,77 @@ __device__ __forceinline__ void store_t(char *row, uint32_t rbytes, int x, const
     }
 }
 
+// ---- intermediate rows in 16 bits (two-pass with a 16-bit intermediate) -----
+// N values per lane: packed in pairs (N/2 words) on the vector path, one per
+// word on the element-wise path.
+template <class TD, int N, bool AL> struct RawTT {
+    static constexpr int NW = (TD::ESZ == 2 && AL) ? N / 2 : N;
+    uint32_t w[NW];
+};
+
+template <class TD, int N, bool AL>
+__device__ __forceinline__ void issue_tt(RawTT<TD, N, AL> &r, const char *row, uint32_t rbytes,
+                                         int x) {
+    static_assert(TD::ESZ == 2, "16-bit intermediates only");
+    const auto rs = row_rsrc(row, rbytes);
+    if constexpr (AL && N == 4) {
+        const u2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, x * 2, 0, 0);
+        r.w[0] = q.x;
+        r.w[1] = q.y;
+    } else if constexpr (AL) {
+#pragma unroll
+        for (int j = 0; j < N / 8; ++j) {
+            const u4 q = __builtin_amdgcn_raw_buffer_load_b128(rs, (x + 8 * j) * 2, 0, 0);
+            r.w[4 * j + 0] = q.x;
+            r.w[4 * j + 1] = q.y;
+            r.w[4 * j + 2] = q.z;
+            r.w[4 * j + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e)
+            r.w[e] = __builtin_amdgcn_raw_buffer_load_b16(rs, (x + e) * 2, 0, 0);
+    }
+}
+
+template <class TD, int N, bool AL>
+__device__ __forceinline__ void decode_tt(const RawTT<TD, N, AL> &r, float (&w)[N]) {
+    if constexpr (AL) {
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            w[2 * i] = dec(TD{}, r.w[i]);
+            w[2 * i + 1] = dec(TD{}, r.w[i] >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e) w[e] = dec(TD{}, r.w[e]);
+    }
+}
+
+// The FP32 row-filter values rounded to TD (RNE, pairwise conversion) and
+// stored; SAUX as for store_t.
+template <class TD, int N, bool AL, int SAUX>
+__device__ __forceinline__ void store_tt(char *row, uint32_t rbytes, int x, const float (&o)[N]) {
+    const auto rs = row_rsrc(row, rbytes);
+    uint32_t q[N / 2];
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) q[i] = enc2(TD{}, o[2 * i], o[2 * i + 1]);
+    if constexpr (AL && N == 4) {
+        __builtin_amdgcn_raw_buffer_store_b64(u2{q[0], q[1]}, rs, x * 2, 0, SAUX);
+    } else if constexpr (AL) {
+#pragma unroll
+        for (int j = 0; j < N / 8; ++j)
+            __builtin_amdgcn_raw_buffer_store_b128(u4{q[4 * j], q[4 * j + 1], q[4 * j + 2], q[4 * j + 3]},
+                                                   rs, (x + 8 * j) * 2, 0, SAUX);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N / 2; ++i) {
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(q[i] & 0xffffu), rs, (x + 2 * i) * 2, 0, SAUX);
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(q[i] >> 16), rs, (x + 2 * i + 1) * 2, 0, SAUX);
+        }
+    }
+}
+
 // ---- output rows in the storage type ------------------------------------
 // SAUX: cache policy (NT streams the output out; 0 keeps it cached when the
 // next kernel reads it, as the copy of the copy-back single pass does).
@@ -308,9 +392,12 @@ template <class D, bool AL, int MODE, bool EDGE, int SAUX = NT>
 struct VBand {
     static constexpr int VEC = D::VEC;
     static constexpr bool DIRECT = MODE == MODE_DIRECT25;
-    static constexpr bool COL = MODE == MODE_COLPASS;
+    static constexpr bool COL = is_colpass(MODE);
     static constexpr int WN = DIRECT ? VEC + 4 : VEC;  // floats per window row
-    using RawIn = typename std::conditional<COL, RawT<VEC, AL>, Raw<D, AL>>::type;
+    using TD = typename TmpOf<MODE>::T;                // the intermediate's type
+    static constexpr bool T16 = COL && TD::ESZ == 2;
+    using RawCol = typename std::conditional<T16, RawTT<TD, VEC, AL>, RawT<VEC, AL>>::type;
+    using RawIn = typename std::conditional<COL, RawCol, Raw<D, AL>>::type;
 
     const ImgDev &im;
     int H, W, x, hoff;
@@ -327,9 +414,9 @@ struct VBand {
         W = im.cols;
         x = xs + lane * VEC;
         if constexpr (COL) {
-            sbase = (const char *)(im.tmp + (int64_t)plane * H * W);
-            sstride = (int64_t)W * 4;
-            sbytes = (uint32_t)W * 4;
+            sbase = (const char *)im.tmp + (int64_t)plane * H * W * TD::ESZ;
+            sstride = (int64_t)W * TD::ESZ;
+            sbytes = (uint32_t)W * TD::ESZ;
         } else {
             sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
             sstride = im.pitch * D::ESZ;
@@ -347,13 +434,17 @@ struct VBand {
     // `row` must already lie in [0, H)
     __device__ __forceinline__ void fetch(RawIn &r, int row) const {
         const char *p = sbase + (int64_t)row * sstride;
-        if constexpr (COL)
+        if constexpr (T16)
+            issue_tt<TD, VEC, AL>(r, p, sbytes, x);
+        else if constexpr (COL)
             issue_t<VEC, AL>(r, p, sbytes, x);
         else
             issue<D>(r, p, sbytes, x, hoff);
     }
     __device__ __forceinline__ void produce(const RawIn &r, float (&w)[WN]) const {
-        if constexpr (COL) {
+        if constexpr (T16) {
+            decode_tt<TD, VEC, AL>(r, w);
+        } else if constexpr (COL) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) w[e] = __uint_as_float(r.w[e]);
         } else if constexpr (DIRECT) {
@@ -458,7 +549,8 @@ __device__ __forceinline__ void band_vertical(const ImgDev &im, int plane, int x
 }
 
 // ---- the two-pass row kernel -----------------------------------------------------
-template <class D, bool AL, bool EDGE>
+// TD: storage type of the intermediate (F32, or F16 / BF16 for the 16-bit form)
+template <class D, bool AL, bool EDGE, class TD = F32>
 struct RBand {
     static constexpr int VEC = D::VEC;
     const ImgDev &im;
@@ -477,9 +569,9 @@ struct RBand {
         sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
         sstride = im.pitch * D::ESZ;
         sbytes = (uint32_t)W * D::ESZ;
-        tbase = (char *)(im.tmp + (int64_t)plane * H * W);
-        tstride = (int64_t)W * 4;
-        tbytes = (uint32_t)W * 4;
+        tbase = (char *)im.tmp + (int64_t)plane * H * W * TD::ESZ;
+        tstride = (int64_t)W * TD::ESZ;
+        tbytes = (uint32_t)W * TD::ESZ;
         const int hl = xs - 2, hr = xs + WAVE * VEC;
         hoff = lane == 0 ? (hl >= 0 ? hl * D::ESZ : OOB)
                          : (lane == WAVE - 1 ? (hr < W ? hr * D::ESZ : OOB) : OOB);
@@ -500,14 +592,17 @@ struct RBand {
 #pragma unroll
             for (int i = 0; i < VEC; ++i) h[i] = cm[i] ? h[i] : 0.0f;
         }
-        store_t<VEC, AL, 0>(tbase + (int64_t)row * tstride, tbytes, x, h);
+        if constexpr (TD::ESZ == 4)
+            store_t<VEC, AL, 0>(tbase + (int64_t)row * tstride, tbytes, x, h);
+        else
+            store_tt<TD, VEC, AL, 0>(tbase + (int64_t)row * tstride, tbytes, x, h);
     }
 };
 
-template <class D, bool AL, bool EDGE, int TH>
+template <class D, bool AL, bool EDGE, int TH, class TD>
 __device__ __forceinline__ void band_rowpass_fixed(const ImgDev &im, int plane, int xs, int y0,
                                                    int lane) {
-    const RBand<D, AL, EDGE> b(im, plane, xs, lane);
+    const RBand<D, AL, EDGE, TD> b(im, plane, xs, lane);
     Raw<D, AL> raw[TH];
 #pragma unroll
     for (int i = 0; i < TH; ++i) b.fetch(raw[i], y0 + i);
@@ -515,10 +610,10 @@ __device__ __forceinline__ void band_rowpass_fixed(const ImgDev &im, int plane, 
     for (int i = 0; i < TH; ++i) b.filter_store(raw[i], y0 + i);
 }
 
-template <class D, bool AL, bool EDGE>
+template <class D, bool AL, bool EDGE, class TD>
 __device__ __forceinline__ void band_rowpass(const ImgDev &im, int plane, int xs, int y0, int y1,
                                              int lane) {
-    const RBand<D, AL, EDGE> b(im, plane, xs, lane);
+    const RBand<D, AL, EDGE, TD> b(im, plane, xs, lane);
     const int rlim = y1 - 1;
     Raw<D, AL> ring[5];
 #pragma unroll
@@ -806,14 +901,15 @@ __device__ __forceinline__ void run_band(const ImgDev &im, int plane, int xs, in
                                          int lane) {
     if constexpr (MODE == MODE_COPY) {
         band_copy<D, AL>(im, plane, xs, y0, y1, lane);
-    } else if constexpr (MODE == MODE_ROWPASS) {
+    } else if constexpr (is_rowpass(MODE)) {
+        using TD = typename TmpOf<MODE>::T;
         if constexpr (TH > 0) {
             if (y1 - y0 == TH) {
-                band_rowpass_fixed<D, AL, EDGE, TH>(im, plane, xs, y0, lane);
+                band_rowpass_fixed<D, AL, EDGE, TH, TD>(im, plane, xs, y0, lane);
                 return;
             }
         }
-        band_rowpass<D, AL, EDGE>(im, plane, xs, y0, y1, lane);
+        band_rowpass<D, AL, EDGE, TD>(im, plane, xs, y0, y1, lane);
     } else {
         if constexpr (TH > 0) {
             if (y1 - y0 == TH) {
@@ -886,7 +982,7 @@ __device__ __forceinline__ void run_strip_band(const ImgDev &im, int plane, int 
     // Does any output of this tile lie in the 2-pixel frame?  (The row pass
     // writes every row, so only columns matter there.)
     const bool col_edge = xs < 2 || xs + WAVE * D::VEC > im.cols - 2;
-    const bool row_edge = MODE != MODE_ROWPASS && (y0 < 2 || y1 > im.rows - 2);
+    const bool row_edge = !is_rowpass(MODE) && (y0 < 2 || y1 > im.rows - 2);
     if constexpr (MODE == MODE_COPY)
         run_band<D, AL, MODE, false, TH>(im, plane, xs, y0, y1, lane);
     else if (col_edge || row_edge)
@@ -1089,6 +1185,11 @@ hipError_t launch_image_m(const ImgDev &im, int mode, int waves, int64_t nblocks
     case MODE_DIRECT25: return launch_image_w<D, AL, MODE_DIRECT25>(im, waves, nblocks, s);
     case MODE_ROWPASS: return launch_image_w<D, AL, MODE_ROWPASS>(im, waves, nblocks, s);
     case MODE_COPY: return launch_image_w<D, AL, MODE_COPY>(im, waves, nblocks, s);
+    // the 16-bit intermediate forms run with one wave per workgroup
+    case MODE_ROWPASS_F16T: return launch_image_th<D, AL, MODE_ROWPASS_F16T, 1>(im, nblocks, s);
+    case MODE_COLPASS_F16T: return launch_image_th<D, AL, MODE_COLPASS_F16T, 1>(im, nblocks, s);
+    case MODE_ROWPASS_BF16T: return launch_image_th<D, AL, MODE_ROWPASS_BF16T, 1>(im, nblocks, s);
+    case MODE_COLPASS_BF16T: return launch_image_th<D, AL, MODE_COLPASS_BF16T, 1>(im, nblocks, s);
     default: return launch_image_w<D, AL, MODE_COLPASS>(im, waves, nblocks, s);
     }
 }

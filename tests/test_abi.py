@@ -103,6 +103,31 @@ def test_empty_images_are_no_ops():
         assert call2(e, a=0, b=0) == cs.CONV_OK
 
 
+def call2x(i, tdt, a=A, b=B, t=0, k=K):
+    return cs.lib().conv_sep5_2pass_ex(ctypes.c_void_p(a), ctypes.c_void_p(b), ctypes.c_void_p(t),
+                                       k, ctypes.byref(i), tdt, None)
+
+
+def test_2pass_ex_validation():
+    """The 16-bit-intermediate entry point: its own argument checks, all
+    before any HIP call."""
+    for bad in (-1, 3, 7):
+        assert call2x(img(), bad) == cs.CONV_EINVAL
+        assert "tmp_dtype" in cs.conv_last_error()
+    hwc = img(planes=3, cols=16, pitch=48, plane_stride=1)
+    assert call2x(hwc, cs.CONV_F16) == cs.CONV_EINVAL
+    assert "FP32 intermediate" in cs.conv_last_error()
+    assert call2x(img(), cs.CONV_F16, k=None) == cs.CONV_EINVAL
+    assert call2x(img(), cs.CONV_BF16, a=0) == cs.CONV_EINVAL
+    assert call2x(img(), cs.CONV_F16, a=A, b=A + 64) == cs.CONV_EALIAS
+    # the 16-bit workspace is half the FP32 one: planes*rows*cols*2 bytes
+    nt = 3 * 16 * 16 * 2
+    assert call2x(img(), cs.CONV_F16, a=A, b=B, t=A - nt + 2) == cs.CONV_EALIAS
+    assert call2x(img(), cs.CONV_F16, a=A, b=B, t=B + 3 * 16 * 16 * 4 - 2) == cs.CONV_EALIAS
+    for e in (img(planes=0), img(rows=0)):
+        assert call2x(e, cs.CONV_F16, a=0, b=0) == cs.CONV_OK
+
+
 def test_2pass_alias_checks():
     n = 3 * 16 * 16 * 4
     assert call2(img(), a=A, b=A + 64) == cs.CONV_EALIAS          # partial overlap
