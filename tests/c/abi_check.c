@@ -1,7 +1,8 @@
 /*
  * abi_check.c -- the C ABI of libconvsep5 used from plain C with HIP device
  * memory (no Python, no torch): fused, direct and two-pass forms, the
- * single pass with copy-back, a two-image batch, and the error path, on a
+ * single pass with copy-back, a two-image batch, the two-pass form with a
+ * 16-bit intermediate, and the error path, on a
  * 3 x 97 x 333 image, each compared with the FP64 oracle of Eq. 1 (arXiv
  * 1711.09791, Section 1; zero border, Section 5), which this test links as
  * test infrastructure.
@@ -26,6 +27,8 @@
 /* the oracle (oracle/conv5_oracle.c) */
 void oracle_conv5_direct(const double *A, double *B, const double *k, int64_t planes,
                          int64_t rows, int64_t cols, int nthreads);
+void oracle_conv5_twopass_q(const double *A, double *B, double *aux, const double *k,
+                            int64_t planes, int64_t rows, int64_t cols, int tfmt);
 
 #define P 3
 #define R 97
@@ -136,6 +139,42 @@ int main(void) {
             if (out2[i] != out[i]) return fail("batch image 1 differs from plane 0 of image 0");
         HIPCHECK(hipFree(d_out2));
         printf("batch: OK\n");
+    }
+
+    /* the two-pass form with a 16-bit intermediate: CONV_F32 is the FP32 form
+     * bit for bit; with pixels 0..3 and binomial taps every intermediate is
+     * exact in FP16 and BF16, so the result equals the oracle's definition
+     * (row pass, one rounding per intermediate, column pass) exactly */
+    {
+        static float out2[N], host3[N];
+        static double a3[N], aux[R * C];
+        if (conv_sep5_2pass_ex(d_in, d_out, NULL, tap_sets[1], &img, CONV_F32, st) != CONV_OK ||
+            conv_sep5_2pass(d_in, d_cb, NULL, tap_sets[1], &img, st) != CONV_OK)
+            return fail("2pass_ex F32");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(out2, d_cb, bytes, hipMemcpyDeviceToHost));
+        if (memcmp(out, out2, bytes) != 0) return fail("2pass_ex F32 differs from 2pass");
+        for (int i = 0; i < N; ++i) {
+            s = s * 1664525u + 1013904223u;
+            host3[i] = (float)(s >> 30);
+            a3[i] = host3[i];
+        }
+        HIPCHECK(hipMemcpy(d_in, host3, bytes, hipMemcpyHostToDevice));
+        const double k64[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+        const int32_t fmts[2] = {CONV_F16, CONV_BF16};
+        for (int f = 0; f < 2; ++f) {
+            HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+            if (conv_sep5_2pass_ex(d_in, d_out, NULL, tap_sets[0], &img, fmts[f], st) != CONV_OK)
+                return fail("2pass_ex 16-bit");
+            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+            oracle_conv5_twopass_q(a3, ref, aux, k64, P, R, C, f + 1);
+            if (compare(out, ref, 1) != 0.0) return fail("2pass_ex 16-bit vs its oracle");
+        }
+        if (conv_sep5_2pass_ex(d_in, d_out, NULL, tap_sets[0], &img, 5, st) != CONV_EINVAL)
+            return fail("bad tmp_dtype accepted");
+        printf("2pass_ex: OK\n");
     }
 
     /* errors come back as a status and a message, before any HIP call */

@@ -1,10 +1,11 @@
 """Seeded random parity sweep on the GPU: each case draws a storage type, a
 layout (dense, pitched, offset/unaligned, row-interleaved 3R x C, packed HWC),
 an entry point and its form (fused, direct, two-pass, copy-back, batch, width
-n, pyramid level) and a shape of 1..700 rows and columns, runs it through the
-C ABI and compares every output element with the FP64 oracle: FP32 within
-max(1e-6, (2n+2)u) relative, 16-bit through the storage gate, and the frame
-exactly +0.0.  The draw is fixed by the case index, so every run checks the
+n, pyramid level, two-pass with a 16-bit intermediate) and a shape of 1..700
+rows and columns, runs it through the C ABI and compares every output element
+with the FP64 oracle: FP32 within max(1e-6, (2n+2)u) relative, 16-bit through
+the storage gate, the 16-bit intermediate form under its own derived bound,
+and the frame exactly +0.0.  The draw is fixed by the case index, so every run checks the
 same cases."""
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ import oracle
 import paper_1711_09791_amd as cs
 from paper_1711_09791_amd import synth
 from tests import gpu_util as gu
+from tests import test_twopass_t16_gpu as t16
 
 pytestmark = pytest.mark.gpu
 
@@ -33,8 +35,8 @@ def draw(case):
         entry = ("fused", "direct", "2pass", "copyback")[rng.integers(0, 4)]
         P = int(rng.integers(2, 5))
     else:
-        entry = ("fused", "direct", "2pass", "copyback", "batch", "width_n", "pyramid")[
-            rng.integers(0, 7)]
+        entry = ("fused", "direct", "2pass", "copyback", "batch", "width_n", "pyramid",
+                 "2pass_t16")[rng.integers(0, 8)]
         P = 3 if layout == "rows3" else int(rng.integers(1, 4))
     if entry == "pyramid" and layout == "rows3":
         layout = "dense"
@@ -107,6 +109,16 @@ def test_random_case(case):
     k = synth.taps_random_n(9200 + case, n)
     print(f"case {case}: {dtype} {layout} {entry} P={P} R={R} C={C} n={n} mode={mode}", flush=True)
 
+    if entry == "2pass_t16":
+        tfmt = ("f16", "bf16")[case % 2]
+        vin, img = place(a, layout, rng)
+        out = like(vin, layout)
+        cs.conv_sep5_2pass_ex(vin, out, k, t16.TCODE[tfmt], img=img)
+        got = gu.to_host_bits(dense(out, layout))
+        ref = oracle.conv5_twopass_t(A64, k.astype(np.float64), tfmt)
+        bound, _ = t16.bound_t16(A64, k, tfmt)
+        t16.check_t16(got, dtype, ref, bound)
+        return
     if entry == "pyramid":
         vin, iin = place(a, layout, rng)
         out = torch.full((P, (R + 1) // 2, (C + 1) // 2), float("nan"), dtype=a.dtype,
