@@ -1,6 +1,7 @@
 """Size limits on the GPU: launches of more than 2^20 workgroups (the grid
-loop), rows at the 2^30-byte limit, and images larger than 4 GiB (64-bit
-offsets); sampled outputs against the FP64 oracle on crops."""
+loop), rows at the 2^30-byte limit, images larger than 4 GiB (64-bit
+offsets), and a packed last strip whose row span sits just under the 2^31
+offset limit; sampled outputs against the FP64 oracle on crops."""
 import gc
 
 import numpy as np
@@ -111,4 +112,44 @@ def test_image_larger_than_4_gib():
         gu.check_f32(f[0, y:y + 1].cpu().numpy(), r[None])
     assert torch.all(f[0, R - 2:] == 0)
     del a, f, host
+    gc.collect()
+
+
+def test_packed_strip_at_the_span_limit():
+    """A last strip of 40 columns packed 4 bands to a wave, in rows of
+    59,652,256 bytes: the buffer resource of a middle band group spans
+    36 rows = 2,147,481,216 bytes, 2,368 below the 2^31 offset limit that
+    packing allows, so the packed path's 32-bit row offsets run at their
+    largest.  Packed == unpacked bitwise; the packed strip and the first
+    strip match the oracle on crops, at the band-group boundaries."""
+    torch = _torch()
+    C = 256 * 58254 + 40
+    R = 72                       # bands of 8: groups of 4 bands = rows 0-31, 32-63, 64-71
+    assert 36 * C * 4 == 2147481216
+    rng = np.random.default_rng(2500)
+    host = rng.random((1, R, C), dtype=np.float32)
+    k = synth.taps_random(2501)
+    a = gu.to_device(host)
+    orig = cs.conv_get_tile_cfg(0, 0).as_dict()
+    try:
+        cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 8, 1)       # packing on
+        p = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, p, k)
+        cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 8, -1)      # packing off
+        u = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, u, k)
+        torch.cuda.synchronize()
+        assert torch.equal(p, u)
+    finally:
+        cs.conv_set_tile_cfg(0, 0, **orig)
+    del u
+    xs = list(range(C - 44, C)) + [0, 1, 2, 3, 4, 255, 256, 257]
+    for y in (0, 1, 2, 30, 31, 32, 33, 62, 63, 64, 65, 69, 70, 71):
+        got = p[0, y, xs].cpu().numpy().astype(np.float64)
+        r = crop_ref(host, k, y, xs)
+        nz = r != 0
+        assert np.all(got[~nz] == 0), y
+        if nz.any():
+            assert np.max(np.abs(got[nz] - r[nz]) / np.abs(r[nz])) <= 1e-6, y
+    del a, p, host
     gc.collect()
