@@ -149,3 +149,33 @@ def test_batch_packed_strips(dtype, mode, restore_cfg):
                 got = gu.to_host_bits(o)
                 assert np.array_equal(got, r), (variant, th, j)
             check(dtype, gu.to_host_bits(outs[1]), bhosts[1], bks[1])
+
+
+def test_packed_every_tile_order(restore_cfg):
+    """Packing with every XCD order (launch order, slabs, chunks of 2..64 band
+    rows) and, for batches, persistent grids: bitwise equal to packing off."""
+    torch = _torch()
+    host = synth.image(5600, 3, 203, 4 * 64 * 4 + 36)       # FP32: last strip 36 columns
+    a = gu.to_device(host)
+    k = synth.taps_random(5601)
+    cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 8, -1)
+    ref = gu.run("fused", a, k)
+    ref_d = gu.run("direct", a, k)
+    for x in (0, 1, 2, 3, 4, 16, 64):
+        for th in (4, 8):
+            cs.conv_set_tile_cfg(0, 0, th, 1, 0, x, 1)
+            assert torch.equal(gu.run("fused", a, k), ref), (x, th)
+            assert torch.equal(gu.run("direct", a, k), ref_d), (x, th)
+    shapes = [(70, 256 + 20), (33, 512 + 100), (129, 60), (41, 1024 + 8)]
+    ins = [gu.to_device(synth.image(5610 + i, 3, h, w)) for i, (h, w) in enumerate(shapes)]
+    ks = [synth.taps_random(5620 + i) for i in range(len(shapes))]
+    cs.conv_set_tile_cfg(0, 1, 8, 1, 0, 8, -1)
+    refs = [gu.nan_like(t) for t in ins]
+    cs.conv_sep5_batch(ins, refs, ks)
+    for p in (0, 4, 16):
+        for x in (0, 1, 2, 8):
+            cs.conv_set_tile_cfg(0, 1, 8, 1, p, x, 1)
+            outs = [gu.nan_like(t) for t in ins]
+            cs.conv_sep5_batch(ins, outs, ks)
+            for j, (o, r) in enumerate(zip(outs, refs)):
+                assert torch.equal(o, r), (p, x, j)
