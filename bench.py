@@ -421,12 +421,12 @@ def bench_serving(torch, cs, synth, args, sizes=None):
                 "throughput_req_per_s": (n - warm) / span, "offered_req_per_s": rate,
                 "submit_lag_p99_us": q(lg, 0.99) * 1e6, **extra}
 
-    def run_server(max_batch, n_streams, max_bytes, rate, n, warm, seed=5):
+    def run_server(max_batch, n_streams, max_bytes, rate, n, warm, seed=5, queue_only=False):
         arr, pin, pout, kk, imgs = requests(n, rate, seed)
         # inputs are static and synchronised: no producer ordering, like the
         # direct-launch baseline
         srv = cs.Server(budget, max_slots=NBUF, n_streams=n_streams, max_batch=max_batch,
-                        max_batch_bytes=max_bytes, producer_wait=False)
+                        max_batch_bytes=max_bytes, producer_wait=False, queue_only=queue_only)
         tickets = (ctypes.c_uint64 * n)()
         lag = (ctypes.c_double * n)()
         check(cs, G.conv_loadgen_serve(srv._h, n, arr, pin, pout, kk, imgs, hs, tickets, lag))
@@ -440,7 +440,9 @@ def bench_serving(torch, cs, synth, args, sizes=None):
                   "device_us": mean("launch_ns", "done_ns"),
                   "mean_batch": sum(t["batch_size"] for t in w) / len(w)}
         return summarize([t["submit_ns"] for t in times], [t["done_ns"] for t in times], list(lag),
-                         n, warm, rate, {"launches": st["launches"], "max_batch_seen": st["max_batch"],
+                         n, warm, rate, {"launches": st["launches"],
+                                         "direct_launches": st["direct_launches"],
+                                         "max_batch_seen": st["max_batch"],
                                          "max_streams_busy": st["max_streams_busy"],
                                          "mean_stages": stages})
 
@@ -456,6 +458,9 @@ def bench_serving(torch, cs, synth, args, sizes=None):
         "batched": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm),
         "batched_8_streams": lambda rate, n, warm: run_server(16, 8, 128 * MB, rate, n, warm),
         "batched_count_cap_only": lambda rate, n, warm: run_server(16, 4, 0, rate, n, warm),
+        # every launch made by the scheduler thread (no launches from submit)
+        "batched_queue_only": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm,
+                                                               queue_only=True),
         "per_image_launch": lambda rate, n, warm: run_direct(1, rate, n, warm),
         "per_image_launch_4_streams": lambda rate, n, warm: run_direct(4, rate, n, warm),
     }

@@ -337,12 +337,17 @@ typedef struct {
                                   streams (an event per submit, see
                                   conv_serve_submit); 0: the caller promises
                                   every input is complete when it submits  */
-    int32_t reserved;
+    int32_t queue_only;        /* 0: a submit that finds nothing queued and
+                                  a stream idle, >= 10 us after the previous
+                                  submit, launches its request itself (the
+                                  scheduler retires it); dense arrivals go
+                                  to the scheduler, which batches them;
+                                  1: every launch is made by the scheduler */
 } conv_serve_cfg;
 
 typedef struct {
     uint64_t submit_ns;  /* host CLOCK_MONOTONIC at submit                    */
-    uint64_t admit_ns;   /* when the scheduler admitted it into a launch      */
+    uint64_t admit_ns;   /* when it was admitted into a launch                */
     uint64_t launch_ns;  /* when that launch was enqueued                     */
     uint64_t done_ns;    /* when the scheduler saw the launch's event done    */
     int32_t batch_size;  /* requests in its launch                            */
@@ -352,7 +357,9 @@ typedef struct {
 typedef struct conv_server conv_server;
 
 conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv);
-/* Non-blocking.  d_in/d_out: device image (FP32/FP16/BF16) as in
+/* Non-blocking (it never waits for the GPU; with queue_only = 0 it may
+ * enqueue the request's launch itself, see conv_serve_cfg).  d_in/d_out:
+ * device image (FP32/FP16/BF16) as in
  * conv_sep5_1pass; k: 5 host taps.  `stream` is the caller's producer stream
  * (NULL: the default stream): with producer_wait = 1, work enqueued on it
  * before this call -- the writes that fill d_in, say -- completes before the
@@ -381,7 +388,8 @@ typedef struct {
     int32_t max_slots_in_flight;  /* high-water mark of admitted requests     */
     int32_t max_batch;            /* largest launch                           */
     int32_t max_streams_busy;     /* most launches in flight at once          */
-    int32_t reserved;
+    int32_t direct_launches;      /* launches a submit made itself (of
+                                     `launches`; counts to 2^31 - 1)          */
 } conv_serve_stats;
 conv_status conv_serve_get_stats(conv_server *srv, conv_serve_stats *stats);
 /* Drains, stops the scheduler and frees the server. */

@@ -49,7 +49,7 @@ class conv_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64),
-                ("producer_wait", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("producer_wait", ctypes.c_int32), ("queue_only", ctypes.c_int32)]
 
 
 class conv_req_times(ctypes.Structure):
@@ -66,10 +66,10 @@ class conv_serve_stats(ctypes.Structure):
                 ("failed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("max_bytes_in_flight", ctypes.c_uint64), ("max_slots_in_flight", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_streams_busy", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("direct_launches", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class ConvError(RuntimeError):
@@ -444,10 +444,10 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                  max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                 producer_wait: bool = True):
+                 producer_wait: bool = True, queue_only: bool = False):
         cfg = conv_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(n_streams),
                              int(max_batch), int(device), int(max_batch_bytes),
-                             int(bool(producer_wait)), 0)
+                             int(bool(producer_wait)), int(bool(queue_only)))
         h = ctypes.c_void_p()
         _check(lib().conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -494,9 +494,9 @@ class Server:
 
 def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                       max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                      producer_wait: bool = True) -> Server:
+                      producer_wait: bool = True, queue_only: bool = False) -> Server:
     return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device, max_batch_bytes,
-                  producer_wait)
+                  producer_wait, queue_only)
 
 
 def conv_serve_submit(srv: Server, d_in, d_out, k, img=None, stream=None) -> int:

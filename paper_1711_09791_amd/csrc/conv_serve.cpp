@@ -14,6 +14,11 @@
 //      stream, after a wait on the producers' events, followed by a
 //      completion event;
 //   4. poll the in-flight events, or spin briefly and then sleep when idle.
+// A submit that finds nothing queued and a stream idle, arriving at least
+// 10 us after the previous one, launches its request itself (unless
+// queue_only is set): at sparse arrivals there is nothing to batch with and
+// the hop to the scheduler only adds latency.  It hands the in-flight launch
+// to the scheduler, which retires it like its own.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
 // same tile code on the same values as a lone call, so it is bitwise
@@ -50,6 +55,9 @@ uint64_t now_ns() {
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3 };
 
 constexpr uint64_t kSpinIdleNs = 2000000;  // scheduler spins 2 ms after going idle
+// A submit launches its request itself only if the previous submit was at
+// least this long ago (longer than a launch takes to enqueue).
+constexpr uint64_t kDirectGapNs = 10000;
 
 struct Req {
     uint64_t ticket = 0;
@@ -89,6 +97,8 @@ struct conv_server {
     std::vector<hipEvent_t> ready_pool;  // producer-stream events
     std::vector<hipEvent_t> event_pool;  // launch-completion events
     std::vector<char> stream_busy;
+    std::vector<Launch> handoff;         // launched by a submitter, not yet polled
+    uint64_t last_submit_ns = 0;
     uint64_t bytes_in_flight = 0;
     int slots_in_flight = 0;
     uint64_t next_ticket = 1;
@@ -100,6 +110,7 @@ struct conv_server {
     void run();
     std::vector<Launch> admit_locked();
     conv_status enqueue(Launch &L, hipEvent_t done_ev);
+    bool launched_locked(Launch &L, conv_status rc, uint64_t t_launch);
 };
 
 // Takes admissible requests off the queue (caller holds mu).
@@ -199,6 +210,34 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     return st;
 }
 
+// Bookkeeping after a launch attempt (caller holds mu): stamps the launch
+// time and returns the ready events; a failed launch fails its requests and
+// frees what admission took.  True if the launch is in flight.
+bool conv_server::launched_locked(Launch &L, conv_status rc, uint64_t t_launch) {
+    for (Req *r : L.reqs) {
+        if (r->ready) ready_pool.push_back(r->ready);
+        r->ready = nullptr;
+        r->t.launch_ns = t_launch;
+    }
+    if (rc != CONV_OK) {
+        for (Req *r : L.reqs) {
+            r->t.done_ns = t_launch;
+            r->state = FAILED;
+        }
+        stats.failed += L.reqs.size();
+        bytes_in_flight -= L.bytes;
+        slots_in_flight -= (int)L.reqs.size();
+        stream_busy[L.stream] = 0;
+        if (L.ev) event_pool.push_back(L.ev);
+        return false;
+    }
+    stats.launches += 1;
+    int busy = 0;
+    for (char b : stream_busy) busy += b != 0;
+    stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)busy);
+    return true;
+}
+
 void conv_server::run() {
     hipSetDevice(device);
     for (;;) {
@@ -230,6 +269,9 @@ void conv_server::run() {
                 stream_busy[L.stream] = 0;
                 event_pool.push_back(L.ev);
             }
+            // launches made by submitters join the polled set
+            for (Launch &L : handoff) inflight.push_back(std::move(L));
+            handoff.clear();
             // 2. admit
             admitted = admit_locked();
         }
@@ -239,29 +281,9 @@ void conv_server::run() {
         const uint64_t t_launch = now_ns();
         {
             std::lock_guard<std::mutex> g(mu);
-            for (size_t i = 0; i < admitted.size(); ++i) {
-                Launch &L = admitted[i];
-                for (Req *r : L.reqs) {
-                    if (r->ready) ready_pool.push_back(r->ready);
-                    r->ready = nullptr;
-                    r->t.launch_ns = t_launch;
-                }
-                if (rc[i] != CONV_OK) {
-                    for (Req *r : L.reqs) {
-                        r->t.done_ns = t_launch;
-                        r->state = FAILED;
-                    }
-                    stats.failed += L.reqs.size();
-                    bytes_in_flight -= L.bytes;
-                    slots_in_flight -= (int)L.reqs.size();
-                    stream_busy[L.stream] = 0;
-                    if (L.ev) event_pool.push_back(L.ev);
-                    continue;
-                }
-                stats.launches += 1;
-                inflight.push_back(std::move(L));
-            }
-            stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)inflight.size());
+            for (size_t i = 0; i < admitted.size(); ++i)
+                if (launched_locked(admitted[i], rc[i], t_launch))
+                    inflight.push_back(std::move(admitted[i]));
         }
         // 4. wait
         if (!inflight.empty()) {
@@ -269,19 +291,20 @@ void conv_server::run() {
             continue;
         }
         std::unique_lock<std::mutex> lk(mu);
-        if (!queue.empty()) continue;
+        // (slots still in flight here belong to a launch a submitter is making)
+        if (!queue.empty() || !handoff.empty() || slots_in_flight > 0) continue;
         idle = true;
         idle_cv.notify_all();
         if (stop) break;
         // Stay awake a little for the next arrival (a futex wake-up costs tens
         // of microseconds), then sleep until a submit.
         const uint64_t idle_from = now_ns();
-        while (queue.empty() && !stop && now_ns() - idle_from < kSpinIdleNs) {
+        while (queue.empty() && handoff.empty() && !stop && now_ns() - idle_from < kSpinIdleNs) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
         }
-        if (queue.empty() && !stop) cv.wait(lk);
+        if (queue.empty() && handoff.empty() && !stop) cv.wait(lk);
     }
 }
 
@@ -293,7 +316,8 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
     *srv = nullptr;
     if (cfg->hbm_budget_bytes == 0 || cfg->max_slots < 1 || cfg->n_streams < 1 ||
         cfg->n_streams > 16 || cfg->max_batch < 1 ||
-        (cfg->producer_wait != 0 && cfg->producer_wait != 1))
+        (cfg->producer_wait != 0 && cfg->producer_wait != 1) ||
+        (cfg->queue_only != 0 && cfg->queue_only != 1))
         return set_error(CONV_EINVAL, "bad server configuration");
     int prev = 0;
     hipGetDevice(&prev);
@@ -368,6 +392,12 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     r->img = *img;
     r->footprint = fp;
     r->t.submit_ns = t_submit;
+    // the direct launch runs on this thread: its current device must be the
+    // server's (descriptors and the CU count follow the current device)
+    int cur = -1;
+    const bool on_device = hipGetDevice(&cur) == hipSuccess && cur == srv->device;
+    Launch direct;
+    bool have_direct = false;
     {
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->stop) {
@@ -383,10 +413,35 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             r->state = DONE;
             srv->stats.completed += 1;
         } else {
+            // Nothing is queued and the previous request came long enough ago
+            // that this thread can spend a launch (~6 us) without falling
+            // behind its arrivals: there is nothing to batch this request
+            // with, so admit and launch it here (if a stream is idle) rather
+            // than wake the scheduler.  Dense arrivals stay with the
+            // scheduler, which batches them.
+            const bool try_direct = !srv->cfg.queue_only && srv->queue.empty() &&
+                                    t_submit - srv->last_submit_ns >= kDirectGapNs;
+            srv->last_submit_ns = t_submit;
             srv->queue.push_back(r);
             srv->idle = false;
+            if (try_direct && on_device) {
+                std::vector<Launch> now = srv->admit_locked();
+                if (!now.empty()) {
+                    direct = std::move(now[0]);
+                    have_direct = true;
+                }
+            }
         }
         *ticket = r->ticket;
+    }
+    if (have_direct) {
+        const conv_status rc = srv->enqueue(direct, direct.ev);
+        const uint64_t t_launch = now_ns();
+        std::lock_guard<std::mutex> g(srv->mu);
+        if (srv->launched_locked(direct, rc, t_launch)) {
+            if (srv->stats.direct_launches < INT32_MAX) srv->stats.direct_launches += 1;
+            srv->handoff.push_back(std::move(direct));
+        }
     }
     srv->cv.notify_one();
     return CONV_OK;

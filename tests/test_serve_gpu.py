@@ -38,7 +38,10 @@ def _wait_all(srv, tickets, timeout_s=60.0):
     return done
 
 
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("queue_only", [False, True])
+def test_results_alone_equal_results_in_the_mix(queue_only):
+    """queue_only = False: submits that find nothing queued and a stream idle
+    launch their request themselves; True: every launch by the scheduler."""
     import torch
 
     torch.manual_seed(0)
@@ -50,7 +53,8 @@ def test_results_alone_equal_results_in_the_mix():
         alone.append(o)
     torch.cuda.synchronize()
     budget = 600 << 20
-    srv = cs.conv_serve_create(budget, max_slots=16, n_streams=4, max_batch=8)
+    srv = cs.conv_serve_create(budget, max_slots=16, n_streams=4, max_batch=8,
+                               queue_only=queue_only)
     try:
         outs = [gu.nan_like(a) for a, _ in reqs]
         tickets = []
@@ -69,7 +73,31 @@ def test_results_alone_equal_results_in_the_mix():
     assert st["max_slots_in_flight"] <= 16 and st["max_batch"] <= 8
     for t in times.values():
         assert t["submit_ns"] <= t["admit_ns"] <= t["launch_ns"] <= t["done_ns"]
+    if queue_only:
+        assert st["direct_launches"] == 0
+    else:
+        assert 1 <= st["direct_launches"] <= st["launches"]
     print("serve stats", st)
+
+
+def test_drain_sees_direct_launches():
+    """A submit that launches its request itself and an immediate drain: the
+    drain returns only once that request is done (the scheduler must not
+    report idle while a submitter is still launching)."""
+    import torch
+
+    srv = cs.conv_serve_create(1 << 30, max_slots=8, n_streams=2, max_batch=4)
+    try:
+        for i in range(60):
+            a = torch.rand(3, 96 + i, 130, device="cuda")
+            o = gu.nan_like(a)
+            t = srv.submit(a, o, synth.taps_random(7000 + i))
+            srv.drain()
+            assert srv.poll(t) is not None, i
+            assert torch.isfinite(o).all()
+        assert srv.stats()["direct_launches"] >= 1
+    finally:
+        srv.destroy()
 
 
 def test_budget_limits_admission_and_launches_overlap():
