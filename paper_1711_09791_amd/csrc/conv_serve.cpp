@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -104,6 +105,10 @@ struct conv_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     bool idle = true;
+    // Bumped (under mu) whenever a submit or destroy changes what the
+    // scheduler must look at, so that its polling loop can skip the lock
+    // while nothing changed: a submitter then rarely finds mu held.
+    std::atomic<uint64_t> seq{0};
     conv_serve_stats stats{};
     std::thread th;
 
@@ -240,6 +245,7 @@ bool conv_server::launched_locked(Launch &L, conv_status rc, uint64_t t_launch) 
 
 void conv_server::run() {
     hipSetDevice(device);
+    uint64_t seen = ~0ull;  // seq when the locked part last ran
     for (;;) {
         // 1. retire finished launches (event queries without the lock)
         std::vector<std::pair<Launch, hipError_t>> finished;
@@ -253,6 +259,14 @@ void conv_server::run() {
             inflight.erase(inflight.begin() + i);
         }
         const uint64_t t_done = now_ns();
+        // Nothing finished and nothing submitted since the last look: the
+        // queue cannot have become admissible, so poll again without mu.
+        const uint64_t s_now = seq.load(std::memory_order_acquire);
+        if (finished.empty() && s_now == seen && !inflight.empty()) {
+            std::this_thread::yield();
+            continue;
+        }
+        seen = s_now;
         std::vector<Launch> admitted;
         {
             std::lock_guard<std::mutex> g(mu);
@@ -276,10 +290,10 @@ void conv_server::run() {
             admitted = admit_locked();
         }
         // 3. launch (no lock)
-        std::vector<conv_status> rc(admitted.size());
-        for (size_t i = 0; i < admitted.size(); ++i) rc[i] = enqueue(admitted[i], admitted[i].ev);
-        const uint64_t t_launch = now_ns();
-        {
+        if (!admitted.empty()) {
+            std::vector<conv_status> rc(admitted.size());
+            for (size_t i = 0; i < admitted.size(); ++i) rc[i] = enqueue(admitted[i], admitted[i].ev);
+            const uint64_t t_launch = now_ns();
             std::lock_guard<std::mutex> g(mu);
             for (size_t i = 0; i < admitted.size(); ++i)
                 if (launched_locked(admitted[i], rc[i], t_launch))
@@ -299,11 +313,11 @@ void conv_server::run() {
         // Stay awake a little for the next arrival (a futex wake-up costs tens
         // of microseconds), then sleep until a submit.
         const uint64_t idle_from = now_ns();
-        while (queue.empty() && handoff.empty() && !stop && now_ns() - idle_from < kSpinIdleNs) {
-            lk.unlock();
+        const uint64_t s_idle = seq.load(std::memory_order_relaxed);
+        lk.unlock();
+        while (seq.load(std::memory_order_acquire) == s_idle && now_ns() - idle_from < kSpinIdleNs)
             std::this_thread::yield();
-            lk.lock();
-        }
+        lk.lock();
         if (queue.empty() && handoff.empty() && !stop) cv.wait(lk);
     }
 }
@@ -424,6 +438,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             srv->last_submit_ns = t_submit;
             srv->queue.push_back(r);
             srv->idle = false;
+            srv->seq.fetch_add(1, std::memory_order_release);
             if (try_direct && on_device) {
                 std::vector<Launch> now = srv->admit_locked();
                 if (!now.empty()) {
@@ -442,6 +457,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             if (srv->stats.direct_launches < INT32_MAX) srv->stats.direct_launches += 1;
             srv->handoff.push_back(std::move(direct));
         }
+        srv->seq.fetch_add(1, std::memory_order_release);
     }
     srv->cv.notify_one();
     return CONV_OK;
@@ -488,6 +504,7 @@ conv_status conv_serve_destroy(conv_server *srv) {
     {
         std::lock_guard<std::mutex> g(srv->mu);
         srv->stop = true;
+        srv->seq.fetch_add(1, std::memory_order_release);
     }
     srv->cv.notify_one();
     if (srv->th.joinable()) srv->th.join();
