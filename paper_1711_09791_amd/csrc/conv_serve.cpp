@@ -192,8 +192,11 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     std::vector<ImgDev> descs;
     int64_t total = 0;
     int dt = 0;
-    conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
-                                 CONV_1PASS_FUSED, tc, &descs, &total, &dt);
+    // a group of one runs the single-image kernel (same tiles, same bits,
+    // less to marshal); larger groups one batch launch
+    conv_status st = n == 1 ? CONV_OK
+                            : build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
+                                          CONV_1PASS_FUSED, tc, &descs, &total, &dt);
     // The launch starts only after each request's producer work.  Events
     // recorded on one stream complete in order, so waiting on the latest
     // request of each producer stream covers the earlier ones.
@@ -210,7 +213,9 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     }
     for (auto &pe : last)
         if (st == CONV_OK && hipStreamWaitEvent(s, pe.second, 0) != hipSuccess) st = CONV_EHIP;
-    if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
+    if (st == CONV_OK)
+        st = n == 1 ? conv_sep5_1pass(ins[0], outs[0], ks.data(), &imgs[0], CONV_1PASS_FUSED, s)
+                    : enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
     if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
     return st;
 }
