@@ -319,9 +319,10 @@ conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_in,
 /* ---------------------------------------------------------------------------
  * Continuous-batching server.  A scheduler thread admits submitted requests in
  * arrival order while a slot is free and their HBM footprint (input + output
- * bytes) fits the budget, packs every admitted request into one persistent
- * batch launch on the next idle stream, and retires requests when the launch's
- * event completes.  Requests that arrive while others run are admitted into
+ * bytes) fits the budget, packs the requests admitted together into one
+ * launch on the next idle stream (the batch kernel; a lone request runs the
+ * single-image kernel), and retires requests when the launch's event
+ * completes.  Requests that arrive while others run are admitted into
  * the next launch, on another stream, so their work overlaps on the device.
  * Each result is bitwise identical to a lone conv_sep5_1pass (fused) call.
  */
@@ -383,7 +384,7 @@ typedef struct {
     uint64_t submitted;           /* accepted submissions                     */
     uint64_t completed;           /* requests whose launch finished           */
     uint64_t failed;              /* requests whose launch failed             */
-    uint64_t launches;            /* batch launches enqueued                  */
+    uint64_t launches;            /* launches enqueued                        */
     uint64_t max_bytes_in_flight; /* high-water mark of admitted footprints   */
     int32_t max_slots_in_flight;  /* high-water mark of admitted requests     */
     int32_t max_batch;            /* largest launch                           */
