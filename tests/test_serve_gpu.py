@@ -80,6 +80,83 @@ def test_results_alone_equal_results_in_the_mix(queue_only):
     print("serve stats", st)
 
 
+SHAPES_MIX = [(3, 37, 300), (1, 4, 9), (3, 0, 10), (2, 77, 131), (3, 130, 517), (1, 1, 1),
+              (3, 64, 256), (2, 5, 5), (3, 91, 1031), (1, 200, 64)]
+
+
+def _mixed_request(i):
+    """Request i of the mixed test: dtypes in runs of five (a launch groups
+    consecutive requests of one dtype), shape i mod 10, so 30 requests take
+    every (dtype, shape) pair; shapes 4 and 9 are an unaligned and a pitched
+    aligned view, each with padding 7 around it."""
+    import torch
+
+    dt = ("f32", "f16", "bf16")[(i // 5) % 3]
+    P, R, C = SHAPES_MIX[i % len(SHAPES_MIX)]
+    host = synth.to_storage(synth.image(8000 + i, P, R, C), dt)
+    dense = gu.to_device(host, dt)
+    k = synth.taps_random(8100 + i)
+    if i % 10 not in (4, 9):
+        return host, dt, dense, gu.nan_like(dense), None, k
+    off = 1 if i % 10 == 4 else 8     # 8 elements: 16-byte aligned in every dtype
+    big_in = torch.full((P, R, C + 16), 7.0, dtype=dense.dtype, device="cuda")
+    a = big_in[:, :, off:off + C]
+    a.copy_(dense)
+    big_out = torch.full((P, R, C + 16), 7.0, dtype=dense.dtype, device="cuda")
+    o = big_out[:, :, off:off + C]
+    o.fill_(float("nan"))
+    return host, dt, a, o, (big_out, off, C), k
+
+
+@pytest.mark.parametrize("queue_only", [False, True])
+def test_mixed_dtypes_ragged_and_empty(queue_only):
+    """FP32, FP16 and BF16 requests of ragged sizes (unaligned widths, images
+    smaller than the filter, an empty one, an unaligned and a pitched view),
+    queued behind a large request on one stream so that later ones launch in
+    groups: each served result equals the lone conv_sep5_1pass call bitwise
+    and the FP64 oracle (FP32 bound, 16-bit gate), and the padding around
+    views is untouched."""
+    import torch
+
+    reqs = [_mixed_request(i) for i in range(30)]
+    blocker = torch.rand(3, 4096, 8192, device="cuda")
+    blocker_out = torch.empty_like(blocker)
+    alone = []
+    for host, dt, a, o, _, k in reqs:
+        r = torch.empty_strided(a.size(), a.stride(), dtype=a.dtype, device="cuda")
+        r.fill_(float("nan"))
+        if a.numel():
+            cs.conv_sep5_1pass(a, r, k)
+        alone.append(r)
+    torch.cuda.synchronize()
+    srv = cs.conv_serve_create(1 << 30, max_slots=12, n_streams=1, max_batch=8,
+                               queue_only=queue_only)
+    try:
+        tickets = [srv.submit(blocker, blocker_out, synth.taps_random(8099))]
+        for host, dt, a, o, _, k in reqs:
+            tickets.append(srv.submit(a, o, k))
+        _wait_all(srv, tickets)
+        st = srv.stats()
+    finally:
+        srv.destroy()
+    assert st["completed"] == 31 and st["failed"] == 0
+    assert st["max_batch"] >= 2, "no request was served in a group"
+    for i, ((host, dt, a, o, pad, k), r) in enumerate(zip(reqs, alone)):
+        if pad is not None:
+            big_out, off, C = pad
+            assert torch.all(big_out[:, :, :off] == 7.0) and torch.all(big_out[:, :, off + C:] == 7.0), i
+        if a.numel() == 0:
+            continue
+        bits = torch.int16 if dt != "f32" else torch.int32
+        assert torch.equal(o.contiguous().view(bits), r.contiguous().view(bits)), (i, dt, a.shape)
+        ref = gu.oracle_of(host, k, dt)
+        got = gu.to_host_bits(o)
+        if dt == "f32":
+            gu.check_f32(got, ref)
+        else:
+            gu.gate16(got, ref, dt)
+
+
 def test_drain_sees_direct_launches():
     """A submit that launches its request itself and an immediate drain: the
     drain returns only once that request is done (the scheduler must not
