@@ -139,3 +139,39 @@ def test_hwc_full_hd_rgb():
     k = synth.taps_random(2101)
     for form in FORMS:
         assert torch.equal(run_hwc(form, h, k).permute(2, 0, 1), run_planar(form, a, k)), form
+
+
+@pytest.mark.parametrize("C", [4, 8, 252, 256, 260, 512, 516, 1028])
+def test_rgb_aligned_strip_widths(C):
+    """Three FP32 channels with 16-byte aligned rows (cols a multiple of 4, the
+    vector path): widths around strip boundaries, heights with partial last
+    bands, dense and as aligned pitched views (padding untouched), in place:
+    each equals the planar fused result bitwise, and one height is checked
+    against the oracle."""
+    torch = _torch()
+    P = 3
+    for R in (5, 6, 9, 13, 37):
+        host = synth.image(2200 + C + R, P, R, C)
+        a = gu.to_device(host)
+        k = synth.taps_random(2201 + C)
+        ref = run_planar("fused", a, k)
+        h = a.permute(1, 2, 0).contiguous()
+        got = run_hwc("fused", h, k).permute(2, 0, 1).contiguous()
+        assert torch.equal(got, ref), (C, R)
+        for pad, off in ((16, 0), (32, 8)):
+            big_in = torch.zeros(R, C * P + pad, device="cuda")
+            big_out = torch.full_like(big_in, 3.0)
+            vin = big_in[:, off:off + C * P].unflatten(1, (C, P))
+            vin.copy_(h)
+            vout = big_out[:, off:off + C * P].unflatten(1, (C, P))
+            run_hwc("fused", vin, k, out=vout)
+            assert torch.equal(vout.permute(2, 0, 1).contiguous(), ref), (C, R, pad, off)
+            mask = torch.ones_like(big_out, dtype=torch.bool)
+            mask[:, off:off + C * P] = False
+            assert torch.all(big_out[mask] == 3.0), (C, R, pad, off)
+        b = h.clone()
+        run_hwc("fused", b, k, out=b)
+        assert torch.equal(b.permute(2, 0, 1).contiguous(), ref), (C, R, "in place")
+        if R == 37:
+            gu.check_f32(got.cpu().numpy(),
+                         oracle.conv5(host.astype(np.float64), k.astype(np.float64), nthreads=0))
