@@ -10,10 +10,11 @@
 //      output bytes) fits the budget, up to max_batch requests of one dtype
 //      and max_batch_bytes per launch (so large frames run alone and small
 //      ones share launches);
-//   3. launch: each admitted group becomes ONE persistent batch launch on its
-//      stream, after a wait on the producers' events, followed by a
-//      completion event;
-//   4. poll the in-flight events, or spin briefly and then sleep when idle.
+//   3. launch: each admitted group becomes ONE batch launch on its stream (a
+//      group of one the single-image kernel), after a wait on the producers'
+//      events, followed by a completion event;
+//   4. poll the in-flight events, or spin briefly and then sleep when idle;
+//      while nothing was submitted or finished the loop skips the lock.
 // A submit that finds nothing queued and a stream idle, arriving at least
 // 10 us after the previous one, launches its request itself (unless
 // queue_only is set): at sparse arrivals there is nothing to batch with and
