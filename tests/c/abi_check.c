@@ -2,7 +2,8 @@
  * abi_check.c -- the C ABI of libconvsep5 used from plain C with HIP device
  * memory (no Python, no torch): fused, direct and two-pass forms, the
  * single pass with copy-back, a two-image batch, the two-pass form with a
- * 16-bit intermediate, and the error path, on a
+ * 16-bit intermediate, the continuous-batching server, and the error path,
+ * on a
  * 3 x 97 x 333 image, each compared with the FP64 oracle of Eq. 1 (arXiv
  * 1711.09791, Section 1; zero border, Section 5), which this test links as
  * test infrastructure.
@@ -175,6 +176,87 @@ int main(void) {
         if (conv_sep5_2pass_ex(d_in, d_out, NULL, tap_sets[0], &img, 5, st) != CONV_EINVAL)
             return fail("bad tmp_dtype accepted");
         printf("2pass_ex: OK\n");
+    }
+
+    /* the server: 12 requests (the whole image and its first plane, with the
+     * inputs written on the caller's stream just before each submit, so that
+     * producer_wait orders the launch after the copy), polled to completion;
+     * each result equals the lone fused call bit for bit */
+    {
+        static float want[N], want1[R * C], got1[R * C];
+        const float *k = tap_sets[1];
+        HIPCHECK(hipMemcpy(d_in, host, bytes, hipMemcpyHostToDevice));
+        if (conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_FUSED, st) != CONV_OK)
+            return fail("server reference");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(want, d_out, bytes, hipMemcpyDeviceToHost));
+        for (int i = 0; i < R * C; ++i) want1[i] = want[i];
+        enum { NREQ = 12 };
+        void *rin[NREQ], *rout[NREQ];
+        uint64_t tickets[NREQ];
+        conv_serve_cfg cfg;
+        memset(&cfg, 0, sizeof cfg);
+        cfg.hbm_budget_bytes = (uint64_t)8 * bytes;
+        cfg.max_slots = 8;
+        cfg.n_streams = 2;
+        cfg.max_batch = 4;
+        cfg.device = -1;
+        cfg.producer_wait = 1;
+        conv_server *srv = NULL;
+        if (conv_serve_create(&cfg, &srv) != CONV_OK) return fail("conv_serve_create");
+        const conv_image plane0 = {1, R, C, CONV_F32, 0, 0};
+        for (int q = 0; q < NREQ; ++q) {
+            const size_t nb = q % 2 ? sizeof(float) * R * C : bytes;
+            HIPCHECK(hipMalloc(&rin[q], nb));
+            HIPCHECK(hipMalloc(&rout[q], nb));
+            HIPCHECK(hipMemsetAsync(rout[q], 0xff, nb, st));
+            HIPCHECK(hipMemcpyAsync(rin[q], d_in, nb, hipMemcpyDeviceToDevice, st));
+            if (conv_serve_submit(srv, rin[q], rout[q], k, q % 2 ? &plane0 : &img, st, &tickets[q]) !=
+                CONV_OK)
+                return fail("conv_serve_submit");
+        }
+        int done = 0;
+        conv_req_times t;
+        for (int spins = 0; done < NREQ && spins < 20000000; ++spins) {
+            done = 0;
+            for (int q = 0; q < NREQ; ++q) {
+                if (!tickets[q]) {
+                    ++done;
+                    continue;
+                }
+                const conv_status ps = conv_serve_poll(srv, tickets[q], &t);
+                if (ps == CONV_OK) {
+                    if (!(t.submit_ns <= t.admit_ns && t.admit_ns <= t.launch_ns &&
+                          t.launch_ns <= t.done_ns) || t.batch_size < 1)
+                        return fail("request times out of order");
+                    tickets[q] = 0;
+                    ++done;
+                } else if (ps != CONV_EAGAIN) {
+                    return fail("conv_serve_poll");
+                }
+            }
+        }
+        if (done < NREQ) return fail("server did not finish");
+        if (conv_serve_drain(srv) != CONV_OK) return fail("conv_serve_drain");
+        conv_serve_stats ss;
+        if (conv_serve_get_stats(srv, &ss) != CONV_OK || ss.completed != NREQ || ss.failed != 0)
+            return fail("server stats");
+        if (conv_serve_poll(srv, 987654321u, &t) != CONV_ENOTFOUND) return fail("unknown ticket");
+        if (conv_serve_destroy(srv) != CONV_OK) return fail("conv_serve_destroy");
+        for (int q = 0; q < NREQ; ++q) {
+            if (q % 2) {
+                HIPCHECK(hipMemcpy(got1, rout[q], sizeof(float) * R * C, hipMemcpyDeviceToHost));
+                if (memcmp(got1, want1, sizeof(float) * R * C) != 0)
+                    return fail("served plane differs from the lone call");
+            } else {
+                HIPCHECK(hipMemcpy(out, rout[q], bytes, hipMemcpyDeviceToHost));
+                if (memcmp(out, want, bytes) != 0) return fail("served image differs from the lone call");
+            }
+            HIPCHECK(hipFree(rin[q]));
+            HIPCHECK(hipFree(rout[q]));
+        }
+        printf("server: OK (%llu launches, largest %d)\n", (unsigned long long)ss.launches,
+               (int)ss.max_batch);
     }
 
     /* errors come back as a status and a message, before any HIP call */
