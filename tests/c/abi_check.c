@@ -2,8 +2,8 @@
  * abi_check.c -- the C ABI of libconvsep5 used from plain C with HIP device
  * memory (no Python, no torch): fused, direct and two-pass forms, the
  * single pass with copy-back, a two-image batch, the two-pass form with a
- * 16-bit intermediate, the continuous-batching server, and the error path,
- * on a
+ * 16-bit intermediate, the continuous-batching server, width 7 in every
+ * form, one pyramid level, and the error path, on a
  * 3 x 97 x 333 image, each compared with the FP64 oracle of Eq. 1 (arXiv
  * 1711.09791, Section 1; zero border, Section 5), which this test links as
  * test infrastructure.
@@ -30,6 +30,8 @@ void oracle_conv5_direct(const double *A, double *B, const double *k, int64_t pl
                          int64_t rows, int64_t cols, int nthreads);
 void oracle_conv5_twopass_q(const double *A, double *B, double *aux, const double *k,
                             int64_t planes, int64_t rows, int64_t cols, int tfmt);
+void oracle_conv_direct_n(const double *A, double *B, const double *K, int n, int64_t planes,
+                          int64_t rows, int64_t cols, int nthreads);
 
 #define P 3
 #define R 97
@@ -257,6 +259,59 @@ int main(void) {
         }
         printf("server: OK (%llu launches, largest %d)\n", (unsigned long long)ss.launches,
                (int)ss.max_batch);
+    }
+
+    /* width 7 (the three separable forms and the full-kernel form) and one
+     * pyramid level, exact case: pixels m/256 with binomial taps make every
+     * FP32 operation exact, so each result equals its oracle bit for bit */
+    {
+        enum { NW = 7, RO = (R + 1) / 2, CO = (C + 1) / 2 };
+        const float k7[NW] = {1 / 64.f, 6 / 64.f, 15 / 64.f, 20 / 64.f, 15 / 64.f, 6 / 64.f, 1 / 64.f};
+        float K7[NW * NW];
+        double K64[NW * NW];
+        for (int a = 0; a < NW; ++a)
+            for (int b = 0; b < NW; ++b) {
+                K64[a * NW + b] = (double)k7[a] * (double)k7[b];
+                K7[a * NW + b] = (float)K64[a * NW + b];
+            }
+        oracle_conv_direct_n(a64, ref, K64, NW, P, R, C, 1);
+        const char *wn[4] = {"sepn fused", "sepn direct", "sepn 2pass", "2d direct"};
+        for (int form = 0; form < 4; ++form) {
+            HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+            conv_status rc;
+            if (form == 0) rc = conv_sepn_1pass(d_in, d_out, k7, NW, &img, CONV_1PASS_FUSED, st);
+            else if (form == 1) rc = conv_sepn_1pass(d_in, d_out, k7, NW, &img, CONV_1PASS_DIRECT25, st);
+            else if (form == 2) rc = conv_sepn_2pass(d_in, d_out, NULL, k7, NW, &img, st);
+            else rc = conv_2d_direct(d_in, d_out, K7, NW, &img, st);
+            if (rc != CONV_OK) return fail(wn[form]);
+            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+            if (compare(out, ref, 1) != 0.0) return fail(wn[form]);
+        }
+        if (conv_sepn_1pass(d_in, d_out, k7, 8, &img, CONV_1PASS_FUSED, st) != CONV_EINVAL)
+            return fail("even width accepted");
+        printf("width 7: OK\n");
+
+        static float pyr[P * RO * CO];
+        const conv_image oimg = {P, RO, CO, CONV_F32, 0, 0};
+        void *d_pyr;
+        HIPCHECK(hipMalloc(&d_pyr, sizeof pyr));
+        HIPCHECK(hipMemsetAsync(d_pyr, 0xff, sizeof pyr, st));
+        if (conv_pyr_down(d_in, &img, d_pyr, &oimg, tap_sets[0], st) != CONV_OK)
+            return fail("conv_pyr_down");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(pyr, d_pyr, sizeof pyr, hipMemcpyDeviceToHost));
+        HIPCHECK(hipFree(d_pyr));
+        const double kb[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+        oracle_conv5_direct(a64, ref, kb, P, R, C, 1);
+        for (int p = 0; p < P; ++p)
+            for (int yo = 0; yo < RO; ++yo)
+                for (int xo = 0; xo < CO; ++xo) {
+                    const float g = pyr[((size_t)p * RO + yo) * CO + xo];
+                    const double r = ref[((size_t)p * R + 2 * yo) * C + 2 * xo];
+                    if (g != (float)r || (r == 0.0 && signbit(g))) return fail("pyramid level vs oracle");
+                }
+        printf("pyramid: OK\n");
     }
 
     /* errors come back as a status and a message, before any HIP call */
