@@ -1,7 +1,8 @@
 /*
  * abi_check.c -- the C ABI of libconvsep5 used from plain C with HIP device
  * memory (no Python, no torch): fused, direct and two-pass forms, the
- * single pass with copy-back, a two-image batch, the two-pass form with a
+ * single pass with copy-back, a two-image batch (eager and as a captured
+ * plan), tile configurations and the tuner, the two-pass form with a
  * 16-bit intermediate, the continuous-batching server, width 7 in every
  * form, one pyramid level, and the error path, on a
  * 3 x 97 x 333 image, each compared with the FP64 oracle of Eq. 1 (arXiv
@@ -142,6 +143,75 @@ int main(void) {
             if (out2[i] != out[i]) return fail("batch image 1 differs from plane 0 of image 0");
         HIPCHECK(hipFree(d_out2));
         printf("batch: OK\n");
+    }
+
+    /* the batch captured as a plan and replayed twice, with eager work in
+     * between; a changed tile configuration and the tuner's pick: every
+     * result equals the default eager one bit for bit */
+    {
+        const float *k = tap_sets[1];
+        static float want[N], want2[R * C], got2[R * C];
+        void *d_o2;
+        HIPCHECK(hipMalloc(&d_o2, sizeof(float) * R * C));
+        const void *ins[2] = {d_in, d_in};
+        void *outs[2] = {d_out, d_o2};
+        const conv_image imgs[2] = {img, {1, R, C, CONV_F32, 0, 0}};
+        float kk[10];
+        memcpy(kk, k, sizeof(float) * 5);
+        memcpy(kk + 5, k, sizeof(float) * 5);
+        if (conv_sep5_batch(2, ins, outs, kk, imgs, CONV_1PASS_FUSED, st) != CONV_OK)
+            return fail("batch (plan reference)");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(want, d_out, bytes, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(want2, d_o2, sizeof(float) * R * C, hipMemcpyDeviceToHost));
+        conv_plan *plan = NULL;
+        if (conv_batch_plan_create(2, ins, outs, kk, imgs, CONV_1PASS_FUSED, &plan) != CONV_OK)
+            return fail("conv_batch_plan_create");
+        for (int rep = 0; rep < 2; ++rep) {
+            HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+            HIPCHECK(hipMemsetAsync(d_o2, 0xff, sizeof(float) * R * C, st));
+            if (conv_batch_plan_launch(plan, st) != CONV_OK) return fail("conv_batch_plan_launch");
+            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+            HIPCHECK(hipMemcpy(got2, d_o2, sizeof(float) * R * C, hipMemcpyDeviceToHost));
+            if (memcmp(out, want, bytes) != 0 || memcmp(got2, want2, sizeof(float) * R * C) != 0)
+                return fail("plan replay differs from the eager batch");
+        }
+        if (conv_batch_plan_destroy(plan) != CONV_OK) return fail("conv_batch_plan_destroy");
+        HIPCHECK(hipFree(d_o2));
+
+        conv_tile_cfg orig, alt, best;
+        if (conv_get_tile_cfg(CONV_F32, 0, &orig) != CONV_OK) return fail("conv_get_tile_cfg");
+        if (conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_FUSED, st) != CONV_OK)
+            return fail("fused (config reference)");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(want, d_out, bytes, hipMemcpyDeviceToHost));
+        alt = orig;
+        alt.rows_per_tile = 13;
+        alt.waves_per_wg = 2;
+        alt.xcd_slabs = 1;
+        if (conv_set_tile_cfg(CONV_F32, 0, &alt) != CONV_OK) return fail("conv_set_tile_cfg");
+        alt.rows_per_tile = 0;
+        if (conv_set_tile_cfg(CONV_F32, 0, &alt) != CONV_EINVAL) return fail("bad tile config accepted");
+        float best_ms = 0.0f;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                const void *tin[1] = {d_in};
+                void *tout[1] = {d_out};
+                if (conv_tune(0, 1, tin, tout, k, &img, 2, st, &best, &best_ms) != CONV_OK ||
+                    !(best_ms > 0.0f))
+                    return fail("conv_tune");
+            }
+            HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+            if (conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_FUSED, st) != CONV_OK)
+                return fail("fused with another tile config");
+            HIPCHECK(hipStreamSynchronize(st));
+            HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+            if (memcmp(out, want, bytes) != 0) return fail("tile config changed the result");
+        }
+        if (conv_set_tile_cfg(CONV_F32, 0, &orig) != CONV_OK) return fail("restoring the tile config");
+        printf("plan, tile configs, tuner: OK (tuned: %d rows, %d waves, %.4f ms)\n",
+               (int)best.rows_per_tile, (int)best.waves_per_wg, (double)best_ms);
     }
 
     /* the two-pass form with a 16-bit intermediate: CONV_F32 is the FP32 form
