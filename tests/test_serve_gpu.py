@@ -157,6 +157,65 @@ def test_mixed_dtypes_ragged_and_empty(queue_only):
             gu.gate16(got, ref, dt)
 
 
+@pytest.mark.parametrize("queue_only", [False, True])
+def test_concurrent_submitters(queue_only):
+    """Four host threads submit to one server at once (ctypes releases the GIL
+    during each call, so submits, launches from submit and the scheduler's
+    polling interleave): every request completes once and equals the lone
+    call bitwise."""
+    import threading
+
+    import torch
+
+    n_threads, per_thread = 4, 24
+    reqs = []
+    for t in range(n_threads):
+        for i in range(per_thread):
+            h, w = (64 + 16 * ((t + i) % 5), 96 + 40 * (i % 7))
+            reqs.append((torch.rand(3, h, w, device="cuda"), synth.taps_random(9000 + 100 * t + i)))
+    alone = []
+    for a, k in reqs:
+        o = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, o, k)
+        alone.append(o)
+    outs = [gu.nan_like(a) for a, _ in reqs]
+    torch.cuda.synchronize()
+    srv = cs.conv_serve_create(1 << 30, max_slots=16, n_streams=3, max_batch=6,
+                               queue_only=queue_only)
+    tickets = [None] * len(reqs)
+    errors = []
+
+    def worker(t):
+        try:
+            torch.cuda.set_device(0)
+            for i in range(per_thread):
+                j = t * per_thread + i
+                a, k = reqs[j]
+                tickets[j] = srv.submit(a, outs[j], k)
+                if i % 6 == 5:
+                    time.sleep(0.0002)
+        except Exception as e:  # reported below; a thread must not die silently
+            errors.append(repr(e))
+
+    try:
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(n_threads)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=60)
+        assert not errors, errors
+        assert all(t is not None for t in tickets)
+        _wait_all(srv, tickets)
+        srv.drain()
+        st = srv.stats()
+    finally:
+        srv.destroy()
+    assert len(set(tickets)) == len(reqs)
+    assert st["submitted"] == len(reqs) and st["completed"] == len(reqs) and st["failed"] == 0
+    for j, (o, r) in enumerate(zip(outs, alone)):
+        assert torch.equal(o, r), j
+
+
 def test_drain_sees_direct_launches():
     """A submit that launches its request itself and an immediate drain: the
     drain returns only once that request is done (the scheduler must not
