@@ -164,17 +164,19 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
                             hipStream_t stream);
 
 /*
- * Many images of different sizes in ONE persistent kernel launch (the
- * device-side counterpart of the paper's task agglomeration over planes,
- * Section 6).  All images must share one dtype; each has its own taps.
+ * Many images of different sizes in ONE kernel launch (the device-side
+ * counterpart of the paper's task agglomeration over planes, Section 6): one
+ * workgroup per tile by default, a persistent grid when the batch tile
+ * configuration asks for one (persist_wgs_per_cu > 0).  All images must share one dtype; each has its own taps.
  *   n            number of images (>= 0; 0 enqueues nothing)
  *   d_in, d_out  host arrays of n device pointers
  *   k            host array of n*5 FP32 taps (image i uses k[5i .. 5i+4])
  *   imgs         host array of n descriptors
  *   mode         CONV_1PASS_FUSED or CONV_1PASS_DIRECT25
  * Each output must not overlap its own input or any other image's output.
- * The per-launch descriptor table is staged through a library-owned pinned
- * ring and copied to device memory on `stream`.
+ * Up to 16 images, the per-image descriptors ride in the kernel argument;
+ * a larger batch stages its descriptor table through a library-owned pinned
+ * ring, copied to device memory on `stream`.
  */
 conv_status conv_sep5_batch(int32_t n, const void *const *d_in,
                             void *const *d_out, const float *k,

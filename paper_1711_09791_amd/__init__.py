@@ -383,7 +383,7 @@ def _batch_args(ins, outs, ks, imgs):
 
 def conv_sep5_batch(ins: Sequence, outs: Sequence, ks: Sequence, imgs=None,
                     mode: int = CONV_1PASS_FUSED, stream=None):
-    """Many images of different sizes in one persistent launch."""
+    """Many images of different sizes in one launch."""
     n, pin, pout, kk, ia = _batch_args(ins, outs, ks, imgs)
     return _check(lib().conv_sep5_batch(n, pin, pout, kk, ia, int(mode), _stream(stream)))
 
