@@ -12,7 +12,7 @@
  * pixel (2,2) and ignores the edges).  Every other output pixel (the 2-pixel
  * frame) is written as +0.0.  The form is a correlation: k[0] weights the
  * neighbour at offset -2 (the tap order of the paper's listings in
- * Sections 4.3 and 4.4).  Images smaller than 5 in either dimension have no
+ * Sections 5.3 and 5.4).  Images smaller than 5 in either dimension have no
  * interior and come out all zeros.
  *
  * Arithmetic: FP32 accumulation in every storage type.  The horizontal and the
@@ -164,6 +164,19 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
                             hipStream_t stream);
 
 /*
+ * Image copy: every element of the image described by *img is copied from
+ * d_in to d_out (same layout), by the streaming tile kernel that performs the
+ * copy-back step of the single pass with copy-back (Section 7: the result
+ * built in B is copied back into A).  It moves the same bytes per
+ * plane-pixel as a fused single pass without the filter, so it is also the
+ * achievable-bandwidth reference for the convolution kernels.
+ *   d_in, d_out  device images; d_out == d_in does nothing; any other
+ *                overlap is CONV_EALIAS.
+ */
+conv_status conv_image_copy(const void *d_in, void *d_out, const conv_image *img,
+                            hipStream_t stream);
+
+/*
  * Many images of different sizes in ONE kernel launch (the device-side
  * counterpart of the paper's task agglomeration over planes, Section 6): one
  * workgroup per tile by default, a persistent grid when the batch tile
@@ -299,24 +312,55 @@ typedef struct {
     int32_t pack_tail;
 } conv_tile_cfg;
 
-/* kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel. */
+/*
+ * kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel.
+ * get/set address the default configuration of (dtype, kind).  set also
+ * drops what the tuner installed for (dtype, kind), so an explicit
+ * configuration applies to every workload size.
+ */
 conv_status conv_get_tile_cfg(int32_t dtype, int32_t kind, conv_tile_cfg *cfg);
 conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *cfg);
 
 /*
- * Autotuner: times every candidate configuration of `kind` on the given
+ * The configuration a call of (dtype, kind) whose input plus output bytes
+ * (summed over a batch) are footprint_bytes runs with: the tuner's choice for
+ * that size class if one is installed (*tuned = 1), else the default
+ * (*tuned = 0; tuned may be NULL).  Size classes: <= 64 MiB, <= 256 MiB (the
+ * GPU's last-level cache), <= 1 GiB, larger.
+ */
+conv_status conv_get_tile_cfg_for(int32_t dtype, int32_t kind, uint64_t footprint_bytes,
+                                  conv_tile_cfg *cfg, int32_t *tuned);
+
+/*
+ * Autotuner (the paper points to auto-tuning for performance portability,
+ * Section 3.2): times every candidate configuration of `kind` on the given
  * workload with HIP events (`reps` timed launches each, after one warm-up),
- * installs the fastest with conv_set_tile_cfg and returns it in *best, with
- * its median time per launch in *best_ms.  kind 0 tunes on image 0 alone
- * (fused 1pass), kind 1 on the whole batch.  Synchronises `stream`.
+ * installs the fastest for the workload's storage type, kind and size class
+ * and returns it in *best, with its median time per launch in *best_ms.
+ * kind 0 tunes on image 0 alone (fused 1pass), kind 1 on the whole batch.
+ * Synchronises `stream`.  Calls of other size classes keep their own choice.
  * The launches reuse the same buffers, so a workload whose input and output
  * fit the GPU's 256 MB last-level cache is timed with a warm cache (where
  * other tile orders win than for images streamed from HBM).
+ * If the environment variable CONV_TUNE_CACHE names a file, every installed
+ * choice is written to it after the run (conv_tune_save).
  */
 conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_in,
                       void *const *d_out, const float *k,
                       const conv_image *imgs, int32_t reps,
                       hipStream_t stream, conv_tile_cfg *best, float *best_ms);
+
+/*
+ * Tuner cache.  save writes every installed tuner choice to `path` as JSON
+ * ({"format": "convsep5-tune-1", "entries": [{"dtype", "kind", "size_class",
+ * the five conv_tile_cfg fields, "ms"}, ...]}), replacing the file
+ * atomically.  load reads such a file and installs its entries (all or
+ * nothing: a malformed file or an out-of-range entry is CONV_EINVAL and
+ * changes nothing; a missing file is CONV_ENOTFOUND).  The file named by
+ * CONV_TUNE_CACHE, if any, is loaded at the library's first use.
+ */
+conv_status conv_tune_save(const char *path);
+conv_status conv_tune_load(const char *path);
 
 /* ---------------------------------------------------------------------------
  * Continuous-batching server.  A scheduler thread admits submitted requests in

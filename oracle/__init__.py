@@ -85,6 +85,8 @@ def _load():
         getattr(lib, f).restype = None
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_last_team.argtypes = []
+    lib.oracle_last_team.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -235,3 +237,9 @@ def round_to(x: np.ndarray, dtype: str) -> np.ndarray:
 def max_threads() -> int:
     """Threads an OpenMP region of the oracle uses by default on this host."""
     return int(_load().oracle_max_threads())
+
+
+def last_team() -> int:
+    """Threads the oracle's last parallel region asked for (its nthreads, or
+    the OpenMP default for nthreads <= 0)."""
+    return int(_load().oracle_last_team())

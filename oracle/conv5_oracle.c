@@ -35,6 +35,20 @@
 
 #define R5 2 /* kernel radius: taps at offsets -2..2 */
 
+#ifdef _OPENMP
+/* Threads of one parallel region: nthreads > 0 asks for exactly that many,
+ * otherwise the OpenMP default.  The count is set per region (num_threads
+ * clause), so a call never changes what later calls get by default; the
+ * last region's team is remembered for oracle_last_team(). */
+static int g_last_team = 1;
+static int team_size(int nthreads)
+{
+    const int t = nthreads > 0 ? nthreads : omp_get_max_threads();
+    g_last_team = t;
+    return t;
+}
+#endif
+
 /*
  * Single-pass form (Section 5.1; Eq. 2 / Eq. 3 of Section 5.2): four nested loops, 25
  * multiply-adds per interior pixel, K[a][b] = k[a] * k[b] evaluated in FP64.
@@ -52,9 +66,8 @@ void oracle_conv5_direct(const double *A, double *B, const double *k,
     if (rows < 2 * R5 + 1 || cols < 2 * R5 + 1)
         return; /* no pixel has a full neighbourhood */
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
-#pragma omp parallel for collapse(2) schedule(static)
+    const int team = team_size(nthreads);
+#pragma omp parallel for collapse(2) schedule(static) num_threads(team)
 #endif
     for (int64_t p = 0; p < planes; ++p) {
         for (int64_t y = R5; y < rows - R5; ++y) {
@@ -130,9 +143,8 @@ void oracle_conv_direct_n(const double *A, double *B, const double *K, int n,
     if (n < 1 || n % 2 == 0 || rows < n || cols < n)
         return;
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
-#pragma omp parallel for collapse(2) schedule(static)
+    const int team = team_size(nthreads);
+#pragma omp parallel for collapse(2) schedule(static) num_threads(team)
 #endif
     for (int64_t p = 0; p < planes; ++p) {
         for (int64_t y = r; y < rows - r; ++y) {
@@ -331,6 +343,16 @@ int oracle_max_threads(void)
 {
 #ifdef _OPENMP
     return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Team size asked for by the last parallel region (1 before any). */
+int oracle_last_team(void)
+{
+#ifdef _OPENMP
+    return g_last_team;
 #else
     return 1;
 #endif

@@ -81,10 +81,12 @@ class ConvError(RuntimeError):
 _lib = None
 
 EXPORTS = (
-    "conv_sep5_2pass", "conv_sep5_2pass_ex", "conv_sep5_1pass", "conv_sep5_batch",
+    "conv_sep5_2pass", "conv_sep5_2pass_ex", "conv_sep5_1pass", "conv_image_copy",
+    "conv_sep5_batch",
     "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
     "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct", "conv_pyr_down",
-    "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_tune",
+    "conv_get_tile_cfg", "conv_set_tile_cfg", "conv_get_tile_cfg_for", "conv_tune",
+    "conv_tune_save", "conv_tune_load",
     "conv_serve_create", "conv_serve_submit", "conv_serve_poll", "conv_serve_drain",
     "conv_serve_destroy", "conv_serve_get_stats", "conv_last_error", "conv_version",
 )
@@ -108,6 +110,7 @@ def lib():
         "conv_sep5_2pass": [vp, vp, vp, fp, imgp, vp],
         "conv_sep5_2pass_ex": [vp, vp, vp, fp, imgp, i32, vp],
         "conv_sep5_1pass": [vp, vp, fp, imgp, ctypes.c_int, vp],
+        "conv_image_copy": [vp, vp, imgp, vp],
         "conv_sep5_batch": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, ctypes.c_int, vp],
         "conv_batch_plan_create": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp,
                                    ctypes.c_int, ctypes.POINTER(vp)],
@@ -119,6 +122,9 @@ def lib():
         "conv_batch_plan_destroy": [vp],
         "conv_get_tile_cfg": [i32, i32, cfgp],
         "conv_set_tile_cfg": [i32, i32, cfgp],
+        "conv_get_tile_cfg_for": [i32, i32, u64, cfgp, ctypes.POINTER(i32)],
+        "conv_tune_save": [ctypes.c_char_p],
+        "conv_tune_load": [ctypes.c_char_p],
         "conv_tune": [i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, i32, vp, cfgp,
                       fp],
         "conv_serve_create": [ctypes.POINTER(conv_serve_cfg), ctypes.POINTER(vp)],
@@ -190,6 +196,16 @@ def _dtype_code(t) -> int:
     return m[t.dtype]
 
 
+def _no_broadcast(shape, strides) -> None:
+    """A zero stride in a dimension of size > 1 (an expanded or broadcast view)
+    repeats memory; the descriptor reads 0 as the dense default and would
+    cover bytes the tensor does not own."""
+    for n, s in zip(shape, strides):
+        if n > 1 and s == 0:
+            raise ValueError(f"zero stride in a dimension of size {n} (broadcast or expanded "
+                             "view); pass a contiguous tensor")
+
+
 def image_of(t) -> conv_image:
     """conv_image describing a [planes, rows, cols] (or [rows, cols]) tensor."""
     if t.dim() in (2, 3) and t.numel() == 0:
@@ -206,6 +222,7 @@ def image_of(t) -> conv_image:
     if C > 1 and sc != 1:
         raise ValueError("columns must be contiguous (unit stride); use image_hwc for "
                          "pixel-interleaved [rows, cols, planes] tensors")
+    _no_broadcast((P, R, C), (sp, sr, sc))
     if P > 1 and C > 1 and sp == 1:
         raise ValueError("plane stride 1 with contiguous columns makes planes overlap")
     if P > 1 and R == 1 and C == 1:
@@ -225,6 +242,7 @@ def image_hwc(t) -> conv_image:
     if t.numel() == 0:
         return conv_image(P, R, C, _dtype_code(t), 0, 1)
     sr, sc, sp = t.stride()
+    _no_broadcast((R, C, P), (sr, sc, sp))
     if (P > 1 and sp != 1) or (C > 1 and sc != P):
         raise ValueError("HWC tensors need contiguous pixels (strides [pitch, planes, 1])")
     return conv_image(P, R, C, _dtype_code(t), int(sr) if R > 1 else C * P, 1)
@@ -287,11 +305,26 @@ def _ptr(x):
 
 # ---- entry points ----------------------------------------------------------------------
 
+def _check_workspace(d_tmp, img: conv_image, esz: int) -> None:
+    """A workspace tensor is raw device memory for planes*rows*cols values of
+    the intermediate's type (esz bytes each): the library writes that many
+    bytes from its start, so it must be contiguous and at least that large."""
+    if d_tmp is None or isinstance(d_tmp, int):
+        return
+    need = int(img.planes) * int(img.rows) * int(img.cols) * esz
+    have = d_tmp.numel() * d_tmp.element_size()
+    if have < need:
+        raise ValueError(f"workspace holds {have} bytes, the intermediate needs {need}")
+    if not d_tmp.is_contiguous():
+        raise ValueError("workspace must be contiguous")
+
+
 def conv_sep5_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, stream=None):
     """Two-pass form: row kernel into the FP32 workspace, then column kernel."""
     if img is None:
         _same_layout(d_in, d_out)
         img = image_of(d_in)
+    _check_workspace(d_tmp, img, 4)
     return _check(lib().conv_sep5_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
                                         ctypes.byref(img), _stream(stream)))
 
@@ -303,6 +336,8 @@ def conv_sep5_2pass_ex(d_in, d_out, k, tmp_dtype: int, d_tmp=None,
     if img is None:
         _same_layout(d_in, d_out)
         img = image_of(d_in)
+    if int(tmp_dtype) in (CONV_F32, CONV_F16, CONV_BF16):
+        _check_workspace(d_tmp, img, 4 if int(tmp_dtype) == CONV_F32 else 2)
     return _check(lib().conv_sep5_2pass_ex(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
                                            ctypes.byref(img), int(tmp_dtype), _stream(stream)))
 
@@ -315,6 +350,16 @@ def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
         img = image_of(d_in)
     return _check(lib().conv_sep5_1pass(_ptr(d_in), _ptr(d_out), _taps(k), ctypes.byref(img),
                                         int(mode), _stream(stream)))
+
+
+def conv_image_copy(d_in, d_out, img: conv_image | None = None, stream=None):
+    """Copy an image with the library's streaming tile kernel (the copy-back
+    step of the single pass with copy-back)."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    return _check(lib().conv_image_copy(_ptr(d_in), _ptr(d_out), ctypes.byref(img),
+                                        _stream(stream)))
 
 
 def conv_sepn_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,
@@ -333,6 +378,7 @@ def conv_sepn_2pass(d_in, d_out, k, d_tmp=None, img: conv_image | None = None, s
     if img is None:
         _same_layout(d_in, d_out)
         img = image_of(d_in)
+    _check_workspace(d_tmp, img, 4)
     taps, n = _taps_n(k)
     return _check(lib().conv_sepn_2pass(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), taps, n,
                                         ctypes.byref(img), _stream(stream)))
@@ -429,8 +475,26 @@ def conv_set_tile_cfg(dtype: int, kind: int, rows_per_tile: int, waves_per_wg: i
     return _check(lib().conv_set_tile_cfg(int(dtype), int(kind), ctypes.byref(c)))
 
 
+def conv_get_tile_cfg_for(dtype: int, kind: int, footprint_bytes: int):
+    """(configuration, tuned) that a call with this input + output byte count runs with."""
+    c = conv_tile_cfg()
+    t = ctypes.c_int32()
+    _check(lib().conv_get_tile_cfg_for(int(dtype), int(kind), int(footprint_bytes),
+                                       ctypes.byref(c), ctypes.byref(t)))
+    return c, bool(t.value)
+
+
+def conv_tune_save(path: str):
+    return _check(lib().conv_tune_save(os.fsencode(path)))
+
+
+def conv_tune_load(path: str):
+    return _check(lib().conv_tune_load(os.fsencode(path)))
+
+
 def conv_tune(kind: int, ins, outs, ks, imgs=None, reps: int = 5, stream=None):
-    """Time every tile configuration on this workload; install and return the best."""
+    """Time every tile configuration on this workload; install the best for
+    its size class and return (configuration, median ms)."""
     n, pin, pout, kk, ia = _batch_args(ins, outs, ks, imgs)
     best = conv_tile_cfg()
     ms = ctypes.c_float()

@@ -1,6 +1,7 @@
 """Build libconvsep5.so in-tree with hipcc for gfx950.
 
     python -m paper_1711_09791_amd.build          # compile (always)
+    python -m paper_1711_09791_amd.build --incremental   # only what changed
 
 Each translation unit is compiled to an object in parallel, then linked into
 ``paper_1711_09791_amd/libconvsep5.so``.  Device code is built with FP
@@ -44,8 +45,18 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _headers_mtime():
+            return obj
     cmd = [_hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -53,11 +64,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libconvsep5.so (always rebuilds)."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source and link libconvsep5.so.  By default everything
+    is recompiled; incremental=True reuses objects newer than their source and
+    every header."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(6, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, incremental), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -65,7 +78,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
     # the serving load generator: a separate library on top of the public ABI
-    obj = _compile("conv_loadgen.cpp")
+    obj = _compile("conv_loadgen.cpp", incremental)
     tmp = LOADGEN_LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", obj, "-o", tmp,
            f"-L{PKG}", "-lconvsep5", "-Wl,-rpath,$ORIGIN", "-lpthread"]
@@ -79,5 +92,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

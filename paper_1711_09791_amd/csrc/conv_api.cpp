@@ -125,12 +125,46 @@ static conv_tile_cfg g_cfg[3][2] = {
     {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
 };
 
+// Configurations the tuner installed, per storage type, kind and workload
+// size class (conv_tune, conv_tune_load); they take precedence over the
+// defaults above for workloads of their class.
+static TunedEntry g_tuned[3][2][kSizeClasses];
+
 conv_tile_cfg get_cfg(int dtype, int kind) {
     std::lock_guard<std::mutex> g(g_cfg_mu);
     return g_cfg[dtype][kind];
 }
 
-static bool cfg_ok(const conv_tile_cfg *c, int kind) {
+int size_class(uint64_t footprint) {
+    const uint64_t MiB = 1ull << 20;
+    return footprint <= 64 * MiB ? 0 : footprint <= 256 * MiB ? 1 : footprint <= 1024 * MiB ? 2 : 3;
+}
+
+conv_tile_cfg get_cfg_for(int dtype, int kind, uint64_t footprint) {
+    load_tune_cache_once();
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    const TunedEntry &t = g_tuned[dtype][kind][size_class(footprint)];
+    return t.valid ? t.cfg : g_cfg[dtype][kind];
+}
+
+TunedEntry get_tuned(int dtype, int kind, int cls) {
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    return g_tuned[dtype][kind][cls];
+}
+
+void put_tuned(int dtype, int kind, int cls, const TunedEntry &e) {
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_tuned[dtype][kind][cls] = e;
+    if (kind == 0) g_tuned[dtype][0][cls].cfg.persist_wgs_per_cu = 0;
+}
+
+void put_default_cfg(int dtype, int kind, const conv_tile_cfg &c) {
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_cfg[dtype][kind] = c;
+    if (kind == 0) g_cfg[dtype][0].persist_wgs_per_cu = 0;
+}
+
+bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
     if (kind == 1 && (c->persist_wgs_per_cu < 0 || c->persist_wgs_per_cu > 32)) return false;
@@ -325,6 +359,25 @@ static conv_status finish_slot(DescSlot *sl, hipStream_t s) {
 }
 
 // ---- batch validation and descriptor building --------------------------------------
+// Input plus output bytes of a batch (images that fail validation count 0;
+// build_batch rejects them).
+uint64_t batch_footprint(int32_t n, const conv_image *imgs) {
+    uint64_t f = 0;
+    for (int32_t i = 0; imgs && i < n; ++i) {
+        Layout L;
+        if (check_image(&imgs[i], &L) == CONV_OK) f += 2 * (uint64_t)L.extent_bytes;
+    }
+    clear_error();
+    return f;
+}
+
+// Tile configuration of a batch launch: the tuned one for its storage type and
+// size class, else the batch default.
+conv_tile_cfg batch_cfg(int32_t n, const conv_image *imgs) {
+    const int dt0 = (n > 0 && imgs && imgs[0].dtype >= 0 && imgs[0].dtype <= 2) ? imgs[0].dtype : 0;
+    return get_cfg_for(dt0, 1, batch_footprint(n, imgs));
+}
+
 conv_status build_batch(int32_t n, const void *const *d_in, void *const *d_out, const float *k,
                         const conv_image *imgs, int mode, const conv_tile_cfg &cfg,
                         std::vector<ImgDev> *descs, int64_t *total, int *dtype_out) {
@@ -450,6 +503,25 @@ conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int d
     return rc;
 }
 
+// The copy kernel over an image of either layout (the copy-back step).  The
+// copy is elementwise: a pixel-interleaved image copies as one plane of
+// cols*planes elements per row.
+hipError_t launch_copy(const void *d_in, void *d_out, const conv_image *img, const Layout &L,
+                       const conv_tile_cfg &cfg, hipStream_t stream) {
+    conv_image flat = *img;
+    Layout LF = L;
+    if (L.hwc) {
+        flat.cols = img->cols * img->planes;
+        flat.planes = 1;
+        flat.plane_stride = 0;
+        LF.ps = (int64_t)img->rows * L.pitch;
+    }
+    ImgDev d;
+    const float k0[5] = {0, 0, 0, 0, 0};
+    const int64_t nblocks = fill_desc(&d, d_in, d_out, nullptr, &flat, LF, k0, cfg);
+    return launch_image(d, img->dtype, MODE_COPY, cfg.waves_per_wg, nblocks, stream);
+}
+
 }  // namespace convsep5
 
 // ==== public entry points ===========================================================
@@ -473,7 +545,7 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     const bool copy_back = d_in == (const void *)d_out;
     if (!copy_back && overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
         return set_error(CONV_EALIAS, "input and output partially overlap");
-    const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    const conv_tile_cfg cfg = get_cfg_for(img->dtype, 0, 2 * (uint64_t)L.extent_bytes);
     const int kmode = mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25;
     ImgDev d;
     if (!copy_back) {
@@ -511,22 +583,26 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
         d.keep_out = 1;
         e = launch_image(d, img->dtype, kmode, cfg.waves_per_wg, nblocks, stream);
     }
-    if (e == hipSuccess) {
-        // the copy is elementwise: a pixel-interleaved image copies as one
-        // plane of cols*planes elements per row
-        conv_image flat = *img;
-        Layout LF = L;
-        if (L.hwc) {
-            flat.cols = img->cols * img->planes;
-            flat.planes = 1;
-            flat.plane_stride = 0;
-            LF.ps = (int64_t)img->rows * L.pitch;
-        }
-        nblocks = fill_desc(&d, scratch, d_out, nullptr, &flat, LF, k, cfg);
-        e = launch_image(d, img->dtype, MODE_COPY, cfg.waves_per_wg, nblocks, stream);
-    }
+    if (e == hipSuccess) e = launch_copy(scratch, d_out, img, L, cfg, stream);
     (void)hipFreeAsync(scratch, stream);
     if (e != hipSuccess) return hip_error(e, "1pass (copy-back) kernel launch");
+    return CONV_OK;
+}
+
+conv_status conv_image_copy(const void *d_in, void *d_out, const conv_image *img,
+                            hipStream_t stream) {
+    clear_error();
+    Layout L;
+    conv_status st = check_image(img, &L);
+    if (st != CONV_OK) return st;
+    if (L.empty) return CONV_OK;
+    if (!d_in || !d_out) return set_error(CONV_EINVAL, "NULL device pointer");
+    if (d_in == (const void *)d_out) return CONV_OK;
+    if (overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
+        return set_error(CONV_EALIAS, "input and output partially overlap");
+    hipError_t e = launch_copy(d_in, d_out, img, L,
+                               get_cfg_for(img->dtype, 0, 2 * (uint64_t)L.extent_bytes), stream);
+    if (e != hipSuccess) return hip_error(e, "copy kernel launch");
     return CONV_OK;
 }
 
@@ -562,7 +638,7 @@ static conv_status twopass(const void *d_in, void *d_out, void *d_tmp, const flo
             return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)tmp_bytes,
                              hipGetErrorString(e));
     }
-    conv_tile_cfg cfg = get_cfg(img->dtype, 0);
+    conv_tile_cfg cfg = get_cfg_for(img->dtype, 0, 2 * (uint64_t)L.extent_bytes);
     int row_mode = MODE_ROWPASS, col_mode = MODE_COLPASS;
     if (tmp_dtype != CONV_F32) {
         cfg.waves_per_wg = 1;
@@ -602,8 +678,7 @@ conv_status conv_sep5_batch(int32_t n, const void *const *d_in, void *const *d_o
     std::vector<ImgDev> descs;
     int64_t total = 0;
     int dtype = 0;
-    const int dt0 = (n > 0 && imgs && imgs[0].dtype >= 0 && imgs[0].dtype <= 2) ? imgs[0].dtype : 0;
-    const conv_tile_cfg cfg = get_cfg(dt0, 1);
+    const conv_tile_cfg cfg = batch_cfg(n, imgs);
     conv_status st = build_batch(n, d_in, d_out, k, imgs, mode, cfg, &descs, &total, &dtype);
     if (st != CONV_OK) return st;
     return enqueue_batch(descs, total, dtype, mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25,
@@ -623,9 +698,22 @@ conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *
     if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
         return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
     if (!cfg_ok(cfg, kind)) return set_error(CONV_EINVAL, "tile configuration out of range");
-    std::lock_guard<std::mutex> g(g_cfg_mu);
-    g_cfg[dtype][kind] = *cfg;
-    if (kind == 0) g_cfg[dtype][0].persist_wgs_per_cu = 0;
+    put_default_cfg(dtype, kind, *cfg);
+    // an explicit configuration replaces what the tuner installed for this
+    // storage type and kind
+    for (int c = 0; c < kSizeClasses; ++c) put_tuned(dtype, kind, c, TunedEntry{});
+    return CONV_OK;
+}
+
+conv_status conv_get_tile_cfg_for(int32_t dtype, int32_t kind, uint64_t footprint_bytes,
+                                  conv_tile_cfg *cfg, int32_t *tuned) {
+    clear_error();
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+        return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
+    load_tune_cache_once();
+    const TunedEntry t = get_tuned(dtype, kind, size_class(footprint_bytes));
+    *cfg = t.valid ? t.cfg : get_cfg(dtype, kind);
+    if (tuned) *tuned = t.valid ? 1 : 0;
     return CONV_OK;
 }
 
@@ -647,8 +735,7 @@ conv_status conv_batch_plan_create(int32_t n, const void *const *d_in, void *con
     std::vector<ImgDev> descs;
     int64_t total = 0;
     int dtype = 0;
-    const int dt0 = (n > 0 && imgs && imgs[0].dtype >= 0 && imgs[0].dtype <= 2) ? imgs[0].dtype : 0;
-    const conv_tile_cfg cfg = get_cfg(dt0, 1);
+    const conv_tile_cfg cfg = batch_cfg(n, imgs);
     conv_status st = build_batch(n, d_in, d_out, k, imgs, mode, cfg, &descs, &total, &dtype);
     if (st != CONV_OK) return st;
     DeviceState *ds = nullptr;

@@ -58,11 +58,9 @@ conv_status run_single(const void *d_in, void *d_out, const TapsN &tp, int n,
     int64_t nblocks = fill_desc_n(&d, d_in, scratch, nullptr, img, L, direct);
     d.keep_out = 1;  // cached stores: the copy reads the scratch next
     e = launch_image_n(d, tp, img->dtype, radius, kmode, nblocks, stream);
-    if (e == hipSuccess) {
-        const conv_tile_cfg cfg = get_cfg(img->dtype, 0);
-        nblocks = fill_desc(&d, scratch, d_out, nullptr, img, L, kNoTaps, cfg);
-        e = launch_image(d, img->dtype, MODE_COPY, cfg.waves_per_wg, nblocks, stream);
-    }
+    if (e == hipSuccess) e = launch_copy(scratch, d_out, img, L,
+                                                 get_cfg_for(img->dtype, 0, 2 * (uint64_t)L.extent_bytes),
+                                                 stream);
     (void)hipFreeAsync(scratch, stream);
     return e == hipSuccess ? CONV_OK : hip_error(e, "width-n (copy-back) kernel launch");
 }

@@ -29,7 +29,29 @@ void clear_error();
 conv_status hip_error(hipError_t e, const char *what);
 conv_status check_image(const conv_image *img, Layout *L);
 bool overlaps(const void *a, int64_t na, const void *b, int64_t nb);
-conv_tile_cfg get_cfg(int dtype, int kind);
+conv_tile_cfg get_cfg(int dtype, int kind);  // the default for (dtype, kind)
+bool cfg_ok(const conv_tile_cfg *c, int kind);
+
+// Tuned configurations, per storage type, kind and size class of the
+// workload's input + output bytes: <= 64 MiB, <= 256 MiB (the GPU's last-level
+// cache), <= 1 GiB, larger.
+constexpr int kSizeClasses = 4;
+struct TunedEntry {
+    int valid = 0;
+    conv_tile_cfg cfg{};
+    float ms = 0.0f;  // the tuner's median time per launch
+};
+int size_class(uint64_t footprint_bytes);
+// The configuration a workload of this footprint runs with: tuned for its
+// class if any, else the default.
+conv_tile_cfg get_cfg_for(int dtype, int kind, uint64_t footprint_bytes);
+TunedEntry get_tuned(int dtype, int kind, int cls);
+void put_tuned(int dtype, int kind, int cls, const TunedEntry &e);
+void put_default_cfg(int dtype, int kind, const conv_tile_cfg &c);
+// Loads the file named by CONV_TUNE_CACHE, once per process (conv_tune.cpp).
+void load_tune_cache_once();
+uint64_t batch_footprint(int32_t n, const conv_image *imgs);
+conv_tile_cfg batch_cfg(int32_t n, const conv_image *imgs);
 void fill_taps(Taps *t, const float *k);
 bool packs_last_strip(int mode, int dtype);
 int batch_flags(const std::vector<ImgDev> &descs);  // kBatchAny*
@@ -44,6 +66,8 @@ int64_t fill_desc_hwc(ImgDev *d, const void *in, void *out, float *tmp, const co
                       const Layout &L, const float *k);
 conv_status reject_hwc(const Layout &L, const char *what);
 int batch_grid(int64_t total, int cus, const conv_tile_cfg &cfg);
+hipError_t launch_copy(const void *d_in, void *d_out, const conv_image *img, const Layout &L,
+                       const conv_tile_cfg &cfg, hipStream_t stream);
 conv_status enqueue_batch(const std::vector<ImgDev> &descs, int64_t total, int dtype, int mode,
                           const conv_tile_cfg &cfg, hipStream_t s);
 

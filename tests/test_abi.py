@@ -342,3 +342,129 @@ def test_image_hwc_binding():
         cs.image_of(torch.zeros(5, 7, 3).permute(2, 0, 1))       # columns not contiguous
     with pytest.raises(ValueError):
         cs.image_of(torch.zeros(40).as_strided((3, 5, 7), (1, 7, 1)))
+
+
+def test_binding_rejects_broadcast_views():
+    """Expanded or broadcast tensors repeat memory through a zero stride; the
+    descriptor would read 0 as the dense default and cover bytes the tensor
+    does not own, so the binding refuses them."""
+    import torch
+
+    plane = torch.zeros(1, 16, 24)
+    with pytest.raises(ValueError, match="zero stride"):
+        cs.image_of(plane.expand(3, 16, 24))
+    with pytest.raises(ValueError, match="zero stride"):
+        cs.image_of(torch.zeros(3, 1, 24).expand(3, 16, 24))
+    with pytest.raises(ValueError, match="zero stride"):
+        cs.image_hwc(torch.zeros(16, 24, 1).expand(16, 24, 3))
+    # a size-1 dimension may carry any stride, including 0
+    d = cs.image_of(plane.expand(1, 16, 24))
+    assert (d.planes, d.rows, d.cols) == (1, 16, 24)
+    out = torch.zeros(3, 8, 8)
+    # the pyramid describes its input without a layout comparison
+    with pytest.raises(ValueError, match="zero stride"):
+        cs.conv_pyr_down(torch.zeros(1, 16, 16).expand(3, 16, 16), out, [0.2] * 5)
+
+
+def test_binding_checks_workspace_size():
+    """A workspace tensor smaller than planes*rows*cols intermediate values is
+    refused before the library would write past it."""
+    import torch
+
+    a = torch.zeros(3, 16, 24)
+    b = torch.zeros(3, 16, 24)
+    k = [0.2] * 5
+    with pytest.raises(ValueError, match="workspace"):
+        cs.conv_sep5_2pass(a, b, k, d_tmp=torch.empty(3 * 16 * 24 - 1))
+    with pytest.raises(ValueError, match="workspace"):
+        cs.conv_sep5_2pass(a, b, k, d_tmp=torch.empty(3 * 16 * 24 // 2, dtype=torch.float16))
+    with pytest.raises(ValueError, match="workspace"):
+        cs.conv_sepn_2pass(a, b, [1.0 / 3] * 3, d_tmp=torch.empty(100))
+    with pytest.raises(ValueError, match="workspace"):
+        cs.conv_sep5_2pass_ex(a, b, k, cs.CONV_F16,
+                              d_tmp=torch.empty(3 * 16 * 24 - 1, dtype=torch.float16))
+    with pytest.raises(ValueError, match="contiguous"):
+        cs.conv_sep5_2pass(a, b, k, d_tmp=torch.empty(3 * 16 * 24 * 2)[::2])
+
+
+def test_image_copy_validation():
+    L = cs.lib()
+    ok = img(planes=3, rows=16, cols=16)
+    assert L.conv_image_copy(A, B, None, None) == cs.CONV_EINVAL
+    assert L.conv_image_copy(None, B, ctypes.byref(ok), None) == cs.CONV_EINVAL
+    assert L.conv_image_copy(A, A + 4, ctypes.byref(ok), None) == cs.CONV_EALIAS
+    assert L.conv_image_copy(A, A, ctypes.byref(ok), None) == cs.CONV_OK      # nothing to do
+    assert L.conv_image_copy(A, B, ctypes.byref(img(rows=0)), None) == cs.CONV_OK
+    assert L.conv_image_copy(A, B, ctypes.byref(img(dtype=7)), None) == cs.CONV_EINVAL
+
+
+def _tune_entry(**kw):
+    e = {"dtype": 0, "kind": 1, "size_class": 3, "rows_per_tile": 16, "waves_per_wg": 2,
+         "persist_wgs_per_cu": 4, "xcd_slabs": 1, "pack_tail": 0, "ms": 0.5}
+    e.update(kw)
+    return e
+
+
+def test_tuner_cache_roundtrip(tmp_path):
+    """The tuner cache file: entries load into their size class only, survive
+    a save/load round trip, and an explicit configuration replaces them.
+    Host tables only (no GPU)."""
+    import json
+
+    d0 = cs.conv_get_tile_cfg(0, 1).as_dict()
+    d1 = cs.conv_get_tile_cfg(1, 0).as_dict()
+    GiB = 1 << 30
+    p = tmp_path / "tune.json"
+    p.write_text(json.dumps({"format": "convsep5-tune-1", "arch": "gfx950", "entries": [
+        _tune_entry(), _tune_entry(dtype=1, kind=0, size_class=0, rows_per_tile=4,
+                                   waves_per_wg=1, persist_wgs_per_cu=0, xcd_slabs=16,
+                                   pack_tail=-1, ms=0.01)]}))
+    try:
+        cs.conv_tune_load(str(p))
+        c, tuned = cs.conv_get_tile_cfg_for(0, 1, 2 * GiB)
+        assert tuned and (c.rows_per_tile, c.waves_per_wg, c.persist_wgs_per_cu,
+                          c.xcd_slabs) == (16, 2, 4, 1)
+        c, tuned = cs.conv_get_tile_cfg_for(0, 1, 100 << 20)           # another class
+        assert not tuned and c.as_dict() == d0
+        c, tuned = cs.conv_get_tile_cfg_for(1, 0, 1 << 20)
+        assert tuned and (c.rows_per_tile, c.xcd_slabs, c.pack_tail) == (4, 16, -1)
+        assert cs.conv_get_tile_cfg(0, 1).as_dict() == d0               # defaults untouched
+        q = tmp_path / "again.json"
+        cs.conv_tune_save(str(q))
+        saved = json.loads(q.read_text())
+        assert saved["format"] == "convsep5-tune-1"
+        got = {(e["dtype"], e["kind"], e["size_class"]): e for e in saved["entries"]}
+        assert got[(0, 1, 3)]["rows_per_tile"] == 16 and got[(1, 0, 0)]["xcd_slabs"] == 16
+        # an explicit configuration drops the tuned entries of its (dtype, kind)
+        cs.conv_set_tile_cfg(0, 1, **{k: v for k, v in d0.items()})
+        assert not cs.conv_get_tile_cfg_for(0, 1, 2 * GiB)[1]
+        assert cs.conv_get_tile_cfg_for(1, 0, 1 << 20)[1]
+        cs.conv_tune_load(str(q))
+        assert cs.conv_get_tile_cfg_for(0, 1, 2 * GiB)[1]
+    finally:
+        cs.conv_set_tile_cfg(0, 1, **d0)
+        cs.conv_set_tile_cfg(1, 0, **d1)
+    assert not cs.conv_get_tile_cfg_for(0, 1, 2 * GiB)[1]
+    assert not cs.conv_get_tile_cfg_for(1, 0, 1 << 20)[1]
+
+
+@pytest.mark.parametrize("bad", [
+    {"format": "other", "entries": []},
+    {"format": "convsep5-tune-1"},
+    {"format": "convsep5-tune-1", "entries": [_tune_entry(rows_per_tile=0)]},
+    {"format": "convsep5-tune-1", "entries": [_tune_entry(waves_per_wg=3)]},
+    {"format": "convsep5-tune-1", "entries": [_tune_entry(size_class=4)]},
+    {"format": "convsep5-tune-1", "entries": [_tune_entry(dtype=3)]},
+    {"format": "convsep5-tune-1", "entries": [_tune_entry(), {"dtype": 0}]},
+])
+def test_tuner_cache_rejects_bad_files(tmp_path, bad):
+    import json
+
+    p = tmp_path / "bad.json"
+    p.write_text(json.dumps(bad))
+    L = cs.lib()
+    assert L.conv_tune_load(os.fsencode(str(p))) == cs.CONV_EINVAL
+    # all or nothing: the valid first entry of the last case was not installed
+    assert not cs.conv_get_tile_cfg_for(0, 1, 2 << 30)[1]
+    assert L.conv_tune_load(os.fsencode(str(tmp_path / "missing.json"))) == cs.CONV_ENOTFOUND
+    assert L.conv_tune_load(None) == cs.CONV_EINVAL

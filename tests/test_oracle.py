@@ -202,6 +202,25 @@ def test_threads_do_not_change_result():
     assert np.array_equal(oracle.conv5(A, k, nthreads=1), oracle.conv5(A, k, nthreads=4))
 
 
+def test_thread_count_does_not_leak_between_calls():
+    """A call's thread count applies to that call only: after serial calls
+    (the wrappers' default) the OpenMP default is unchanged, and an
+    nthreads=0 call takes the full default team."""
+    default = oracle.max_threads()
+    A = np.random.default_rng(24).random((2, 20, 20))
+    k = np.full(5, 0.2)
+    oracle.conv5(A, k)
+    oracle.conv_direct_n(A, np.full((3, 3), 1.0 / 9))
+    assert oracle.last_team() == 1
+    assert oracle.max_threads() == default
+    oracle.conv5(A, k, nthreads=0)
+    assert oracle.last_team() == default
+    oracle.conv5(A, k, nthreads=3)
+    assert oracle.last_team() == 3 and oracle.max_threads() == default
+    oracle.conv_direct_n(A, np.full((3, 3), 1.0 / 9), nthreads=0)
+    assert oracle.last_team() == default
+
+
 # ---- storage decoding and rounding ---------------------------------------
 
 def test_decode_f16_all_patterns():
