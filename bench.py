@@ -8,29 +8,35 @@ filter, on-chip intermediate, column filter, border, output store); `value` is
 its MPix/s.  Inputs are resident in HBM; timed launches rotate over several
 input/output buffer sets so the working set exceeds the 256 MB Infinity Cache.
 
-Also measured and reported in the same JSON line:
+Also measured (the headline line carries a compact summary; every figure goes
+to --detail-out, or to one stderr line):
   forms      the two-pass form (HBM intermediate), the two-pass form with a
-             16-bit intermediate, the direct 25-tap form and a device copy of
-             the same bytes (the achievable ceiling);
-  precision  the fused form with FP16 and BF16 storage (FP32 accumulation);
-  batch      64 uneven images (H, W = 8*U{30..270}) in one persistent launch
-             (FP32, and the same images stored as FP16 and BF16), eager
-             (FP32 also as a captured graph), against one launch per image;
+             16-bit intermediate, the direct 25-tap form, the copy-back single
+             pass, the in-place two-pass, the library's own image copy of the
+             same bytes (the achievable ceiling) and torch's copy; every form
+             also against the problem's minimum of 8 B per plane-pixel; the
+             fused form also cache-warm (one buffer set);
+  small      3x256x256: microseconds per call of each form, cold and warm,
+             queued and as a lone round trip, beside an empty kernel's launch;
+  precision  the image stored as FP16 and BF16 (FP32 accumulation);
+  batch      64 uneven images (H, W = 8*U{30..270}) in one launch (FP32,
+             and the same images stored as FP16 and BF16), eager (FP32 also
+             as a captured graph), with the default and the autotuned tile
+             configuration, against one launch per image;
   serving    Poisson arrivals of 640x480 .. 3840x2160 frames, each with its
              own taps: p50/p99 latency of the continuous-batching server
-             against the same server restricted to one image per launch, at
-             0.5x and 0.8x of the batched server's measured capacity;
+             against one launch per request (1 or 4 streams), at 0.5x and
+             0.8x of the batched server's measured capacity; and 640x480 only;
   widths     odd widths n = 1..9 on the same image: fused, two-pass and
              direct (n*n terms) separable forms and a full non-separable
              n x n kernel, each against the HBM and the FP32 ALU roofline
              (the O(n) vs O(n^2) trade-off of Section 5.1);
-  hwc        the same image stored pixel-interleaved (packed RGB), fused and
-             two-pass, against the planar forms;
-  pyramid    one blur + 2x decimation level of the same image (FP32, FP16):
-             input read once, a quarter of it written;
-  cpu_baseline  the FP64 oracle on the host cores, on the whole image.
+  hwc        the same image stored pixel-interleaved (packed RGB);
+  pyramid    one blur + 2x decimation level of the same image (FP32, FP16);
+  cpu_baseline  the FP64 oracle on the host cores (all, and one) on the image
+             and on the 64-image batch.
 
-Prints ONE JSON line.  Run with no flags for the default configuration.
+Prints ONE JSON line on stdout.  Run with no flags for the default configuration.
 """
 from __future__ import annotations
 
@@ -63,15 +69,17 @@ def parse():
     # (~25 ms) of this kernel; 1000 warm-up launches reach the steady state.
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--sets", type=int, default=3, help="rotating buffer sets")
-    ap.add_argument("--forms", default="fused,2pass,direct25,copy,1pass_copyback,2pass_inplace,"
-                                       "2pass_t16")
+    ap.add_argument("--forms", default="fused,2pass,direct25,copy,torch_copy,1pass_copyback,"
+                                       "2pass_inplace,2pass_t16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, widths, batch and serving measurements")
-    ap.add_argument("--extras", default="precision,widths,hwc,pyramid,batch,serving",
+    ap.add_argument("--extras", default="small,precision,widths,hwc,pyramid,batch,serving",
                     help="comma list of extra measurements to run")
-    ap.add_argument("--warm", action="store_true",
-                    help="also time the fused form on one buffer set (cache-warm)")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the cache-warm timing of the fused form on one buffer set")
+    ap.add_argument("--detail-out", default=None,
+                    help="write every figure as JSON to this file (default: one line on stderr)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--cpu-min-s", type=float, default=10.0,
@@ -167,10 +175,17 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
         "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % S], pout[i % S], ptmp, kk, pimg, hs)),
         "2pass_t16": lambda i: check(cs, L.conv_sep5_2pass_ex(pin[i % S], pout[i % S], ptmp, kk, pimg,
                                                               t16, hs)),
-        "copy": lambda i: outs[i % S].copy_(ins[i % S]),
+        # the library's own streaming copy of the same bytes: the achievable ceiling
+        "copy": lambda i: check(cs, L.conv_image_copy(pin[i % S], pout[i % S], pimg, hs)),
+        "torch_copy": lambda i: outs[i % S].copy_(ins[i % S]),
     }
+    # bytes each form moves by its own definition (the two-pass forms count
+    # their intermediate, written and read back) ...
     alg_bytes = {"fused": 2 * esz, "direct25": 2 * esz, "2pass": 2 * esz + 8, "copy": 2 * esz,
-                 "1pass_copyback": 4 * esz, "2pass_inplace": 2 * esz + 8, "2pass_t16": 2 * esz + 4}
+                 "torch_copy": 2 * esz, "1pass_copyback": 4 * esz, "2pass_inplace": 2 * esz + 8,
+                 "2pass_t16": 2 * esz + 4}
+    # ... and the problem's minimum: read the image once, write the result once
+    min_bytes = 2 * esz * P * R * C
     launches = {"2pass": 2, "2pass_inplace": 2, "1pass_copyback": 2, "2pass_t16": 2}
     res = {}
     for name in forms:
@@ -184,13 +199,22 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
             "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
             "alg_bytes_per_step": nbytes,
             "alg_GBps": nbytes / (avg * 1e-3) / 1e9,
-            "frac_of_hbm_peak": nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            # against the problem's minimum bytes: comparable across forms
+            "frac_of_hbm_peak": min_bytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
         }
-    if "fused" in res and getattr(args, "warm", False):
+        if nbytes != min_bytes:
+            # the form's own bytes over the time; for the two-pass forms most of
+            # the intermediate is read back from the Infinity Cache, so this is
+            # a memory-system rate, not an HBM-only one
+            res[name]["own_bytes_frac_of_peak"] = nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if "fused" in res and not getattr(args, "no_warm", False):
+        # warm: the same input and output every launch (402 MB for FP32, of which
+        # the 256 MB Infinity Cache keeps part); cold: the rotating sets above
         fn = lambda i: check(cs, L.conv_sep5_1pass(pin[0], pout[0], kk, pimg, 0, hs))  # noqa: E731
         res["fused"]["warm_same_buffers_avg_launch_ms"] = timed(torch, fn, args.steps, args.warmup) / args.steps
-    if "fused" in res and "copy" in res:
-        res["fused"]["frac_of_copy"] = res["copy"]["avg_launch_ms"] / res["fused"]["avg_launch_ms"]
+    for c in ("copy", "torch_copy"):
+        if "fused" in res and c in res:
+            res["fused"]["frac_of_" + c] = res[c]["avg_launch_ms"] / res["fused"]["avg_launch_ms"]
     eq = None
     if "fused" in res and "2pass" in res:
         o1, o2 = torch.empty_like(base), torch.empty_like(base)
@@ -200,6 +224,60 @@ def bench_image(torch, cs, host, k, args, dtype=None, forms=("fused", "2pass", "
         eq = bool(torch.equal(o1, o2))
     del ins, outs, tmp
     return res, eq
+
+
+def bench_small(torch, cs, synth, args):
+    """The small configuration (3x256x256 FP32, seed 0, taps [1,4,6,4,1]/16):
+    microseconds per call of each form, next to a launch of an empty kernel
+    (the GPU's fixed cost per call, as the paper's empty tasks and kernels
+    measure the runtimes' overhead, Section 6 Table 2); compute = call - empty.
+    gpu_us: calls queued back to back (events around n calls), warm (one
+    buffer set, 1.5 MB, held in cache) and cold (256 rotating sets, 403 MB,
+    more than the 256 MB Infinity Cache).  host_us: median submit-to-done
+    latency of a lone call (launch + stream synchronisation), native clock."""
+    G = cs.loadgen_lib()
+    L = cs.lib()
+    Ps, Rs, Cs = 3, 256, 256
+    host = synth.image(0, Ps, Rs, Cs)
+    k = synth.taps_binomial()
+    base = torch.from_numpy(host).cuda()
+    out = torch.empty_like(base)
+    tmp = torch.empty(Ps * Rs * Cs, device="cuda")
+    img = cs.image_of(base)
+    kk = (ctypes.c_float * 5)(*[float(v) for v in k])
+    hs = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    n = 2000
+    res = {}
+    for form, name in ((0, "empty_kernel"), (1, "fused"), (2, "direct25"), (3, "2pass")):
+        g, h = ctypes.c_double(), ctypes.c_double()
+        check(cs, G.conv_loadgen_call_latency(form, n, base.data_ptr(), out.data_ptr(), tmp.data_ptr(),
+                                              kk, ctypes.byref(img), hs, ctypes.byref(g),
+                                              ctypes.byref(h)))
+        res[name] = {"gpu_us_warm": g.value, "host_us": h.value}
+    # cold: rotate over enough buffer sets that no launch finds its bytes in a cache
+    NS = 256
+    ins = [base.clone() for _ in range(NS)]
+    outs = [torch.empty_like(base) for _ in range(NS)]
+    tmps = [torch.empty(Ps * Rs * Cs, device="cuda") for _ in range(NS)]
+    pin = [ctypes.c_void_p(t.data_ptr()) for t in ins]
+    pout = [ctypes.c_void_p(t.data_ptr()) for t in outs]
+    ptmp = [ctypes.c_void_p(t.data_ptr()) for t in tmps]
+    pimg = ctypes.byref(img)
+    fns = {
+        "fused": lambda i: check(cs, L.conv_sep5_1pass(pin[i % NS], pout[i % NS], kk, pimg, 0, hs)),
+        "direct25": lambda i: check(cs, L.conv_sep5_1pass(pin[i % NS], pout[i % NS], kk, pimg, 1, hs)),
+        "2pass": lambda i: check(cs, L.conv_sep5_2pass(pin[i % NS], pout[i % NS], ptmp[i % NS], kk,
+                                                       pimg, hs)),
+    }
+    for name, fn in fns.items():
+        res[name]["gpu_us_cold"] = 1e3 * timed(torch, fn, 4 * NS, NS) / (4 * NS)
+    e = res["empty_kernel"]
+    for name in fns:
+        r = res[name]
+        r["compute_gpu_us_warm"] = r["gpu_us_warm"] - e["gpu_us_warm"]
+        r["compute_host_us"] = r["host_us"] - e["host_us"]
+    del ins, outs, tmps
+    return {"workload": f"3x{Rs}x{Cs} FP32, seed 0, k=[1,4,6,4,1]/16", "calls": n, "results": res}
 
 
 def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
@@ -351,6 +429,15 @@ def bench_batch(torch, cs, synth, args):
                 check(cs, L.conv_sep5_1pass(a, o, k, im, 0, hs))
 
         t_lone = timed(torch, lone, steps, warm)
+        # the autotuner on this batch (kind 1): installs its choice for the
+        # batch's storage type and size class; the eager launch is timed again
+        # with it, then the default is restored
+        dcode = {"f32": 0, "f16": 1, "bf16": 2}[dt]
+        default_cfg = cs.conv_get_tile_cfg(dcode, 1)
+        tuned_cfg, _ = cs.conv_tune(1, ins, outs, ks, reps=5)
+        t_tuned = timed(torch, lambda i: check(cs, L.conv_sep5_batch(n, pin, pout, kk, imgs, 0, hs)),
+                        steps, warm)
+        cs.conv_set_tile_cfg(dcode, 1, **default_cfg.as_dict())
         ms_e, ms_l = t_eager / steps, t_lone / steps
         r = {
             "images": 64, "mpix": pix / 1e6, "alg_bytes": nbytes,
@@ -361,6 +448,9 @@ def bench_batch(torch, cs, synth, args):
             "eager_alg_GBps": nbytes / (ms_e * 1e-3) / 1e9,
             "eager_frac_of_hbm_peak": nbytes / (ms_e * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "speedup_vs_per_image": ms_l / ms_e,
+            "tuned_cfg": tuned_cfg.as_dict(),
+            "tuned_eager_ms": t_tuned / steps,
+            "tuned_eager_frac_of_hbm_peak": nbytes / (t_tuned / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         }
         if t_graph is not None:
             ms_g = t_graph / steps
@@ -480,27 +570,130 @@ def bench_serving(torch, cs, synth, args, sizes=None):
     return out
 
 
-def cpu_baseline(oracle, np, host, k, args):
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu's 'Model name'), from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(oracle, np, synth, host, k, args):
+    """The FP64 oracle (direct 25-term sum, OpenMP over plane x row) on the
+    host: the 3x4096x4096 image on every core the oracle's OpenMP team has and
+    on one core, and the 64-image batch on every core and (a sample of 16 of
+    its images) on one core; median of 3 runs each (the all-core image repeated
+    until --cpu-min-s / 3 has passed)."""
+    def med(fn, min_s=0.0, reps=3):
+        times = []
+        t_start = time.perf_counter()
+        while len(times) < reps or (time.perf_counter() - t_start < min_s and len(times) < 200):
+            t = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t)
+        times.sort()
+        return times[len(times) // 2], len(times)
+
     A64 = host.astype(np.float64)
     k64 = k.astype(np.float64)
-    times = []
-    t_start = time.perf_counter()
-    while (len(times) < 3 or time.perf_counter() - t_start < args.cpu_min_s) and len(times) < 200:
-        t = time.perf_counter()
-        oracle.conv5(A64, k64, nthreads=0)
-        times.append(time.perf_counter() - t)
-        if time.perf_counter() - t_start > 3 * args.cpu_min_s:
-            break
-    times.sort()
-    med = times[len(times) // 2]
+    team = oracle.max_threads()
+    t_all, n_all = med(lambda: oracle.conv5(A64, k64, nthreads=0), args.cpu_min_s / 3)
+    t_one, n_one = med(lambda: oracle.conv5(A64, k64, nthreads=1))
+    shapes = synth.batch_shapes(3, 64)
+    imgs = [(synth.image(100 + i, 3, h, w).astype(np.float64), synth.taps_random(200 + i).astype(np.float64))
+            for i, (h, w) in enumerate(shapes)]
+    pix = sum(h * w for h, w in shapes)
+    sample = imgs[::4]
+    spix = sum(a.shape[1] * a.shape[2] for a, _ in sample)
+
+    def batch(items, nt):
+        for a, kb in items:
+            oracle.conv5(a, kb, nthreads=nt)
+
+    b_all, _ = med(lambda: batch(imgs, 0))
+    b_one, _ = med(lambda: batch(sample, 1))
     return {
-        "value": (R * C) / med / 1e6,
+        "value": (R * C) / t_all / 1e6,
         "unit": "MPix/s",
-        "cores": oracle.max_threads(),
+        "cores": team,
         "kind": "oracle",
-        "sample": f"whole 3x{R}x{C} image, FP64 direct 25-term oracle (OpenMP over plane x "
-                  f"row), median of {len(times)} run(s), {med:.3f} s each",
+        "sample": f"whole 3x{R}x{C} FP32 image (as FP64), FP64 direct 25-term oracle, OpenMP over "
+                  f"plane x row on {team} threads, median of {n_all} runs ({t_all:.3f} s each)",
+        "cpu_model": cpu_model(),
+        "one_core_mpix_per_s": (R * C) / t_one / 1e6,
+        "batch64_mpix_per_s": pix / b_all / 1e6,
+        "batch64_one_core_mpix_per_s": spix / b_one / 1e6,
+        "batch64_one_core_sample": f"16 of the 64 images (every 4th, {spix / 1e6:.1f} MPix)",
     }
+
+
+def r3(x):
+    """Rounds for the headline line: 4 significant digits."""
+    return None if x is None else float(f"{x:.4g}")
+
+
+def cfg_str(c):
+    """A tile configuration in one short string."""
+    return ("rows{rows_per_tile} waves{waves_per_wg} persist{persist_wgs_per_cu} "
+            "xcd{xcd_slabs} pack{pack_tail}").format(**c)
+
+
+def summarize(forms, extras, eq):
+    """The compact per-configuration figures that go into the headline line;
+    everything else goes to the detail output."""
+    us = lambda v: r3(v * 1e3)  # noqa: E731  (ms -> us)
+    out = {
+        "c2_us": {n: us(v["ms_per_step"]) for n, v in forms.items()},
+        # against the problem's 8 B per plane-pixel (read once, write once) for every form
+        "c2_frac_hbm_8B": {n: r3(v["frac_of_hbm_peak"]) for n, v in forms.items()},
+        # the two-pass on its own 16 B (intermediate mostly from the Infinity Cache)
+        "c2_2pass_memsys_frac_16B": r3(forms.get("2pass", {}).get("own_bytes_frac_of_peak")),
+        "fused_equals_2pass_bitwise": eq,
+    }
+    f = forms.get("fused", {})
+    out["fused_frac_of_library_copy"] = r3(f.get("frac_of_copy"))
+    out["fused_frac_of_torch_copy"] = r3(f.get("frac_of_torch_copy"))
+    if "warm_same_buffers_avg_launch_ms" in f:
+        out["fused_us_cold_warm"] = [us(f["avg_launch_ms"]), us(f["warm_same_buffers_avg_launch_ms"])]
+    sm = extras.get("small")
+    if sm:
+        rs = sm["results"]
+        out["c1_us_per_call"] = {"cols": "gpu_cold, gpu_warm, host_roundtrip",
+                                 **{n: [r3(v.get("gpu_us_cold")), r3(v["gpu_us_warm"]), r3(v["host_us"])]
+                                    for n, v in rs.items()}}
+        out["c1_compute_us_warm"] = {n: r3(v["compute_gpu_us_warm"]) for n, v in rs.items()
+                                     if "compute_gpu_us_warm" in v}
+    pr = extras.get("precision")
+    if pr:
+        out["c4_us_per_image"] = {d: {n: us(v["ms_per_step"]) for n, v in r.items()} for d, r in pr.items()}
+        out["c4_fused_frac_of_hbm_peak"] = {d: r3(r["fused"]["frac_of_hbm_peak"]) for d, r in pr.items()}
+    b = extras.get("batch")
+    if b:
+        out["c3_batch64"] = {
+            "f32": {"eager_ms": r3(b["eager_ms"]), "graph_ms": r3(b.get("graph_ms")),
+                    "per_image_ms": r3(b["per_image_launches_ms"]), "tuned_ms": r3(b["tuned_eager_ms"]),
+                    "frac": r3(b["eager_frac_of_hbm_peak"]), "graph_frac": r3(b.get("graph_frac_of_hbm_peak")),
+                    "tuned_cfg": cfg_str(b["tuned_cfg"]), "default_cfg": cfg_str(b["tile_cfg"])},
+            **{d: {"eager_ms": r3(v["eager_ms"]), "per_image_ms": r3(v["per_image_launches_ms"]),
+                   "tuned_ms": r3(v["tuned_eager_ms"]), "frac": r3(v["eager_frac_of_hbm_peak"])}
+               for d, v in b["16bit"].items()},
+        }
+    for key, name in (("serving", "c5_mixed"), ("serving_small_frames", "c5_640x480")):
+        sv = extras.get(key)
+        if not sv:
+            continue
+        pol = {"batched": "batched", "per_image_launch": "per_image_1s",
+               "per_image_launch_4_streams": "per_image_4s"}
+        o = {"capacity_req_per_s": {a: r3(sv["capacity_req_per_s"][p]) for p, a in pol.items()}}
+        for lvl, d in sv["levels"].items():
+            o[lvl.split("_")[0] + "_p50_p99_us"] = {a: [r3(d[p]["p50_us"]), r3(d[p]["p99_us"])]
+                                                   for p, a in pol.items()}
+        out[name] = o
+    return out
 
 
 def main():
@@ -526,6 +719,9 @@ def main():
 
     extras = {}
     want = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    if "small" in want:
+        extras["small"] = bench_small(torch, cs, synth, args)
+        progress("small (3x256x256) done")
     if "precision" in want:
         prec = {}
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
@@ -554,27 +750,30 @@ def main():
 
     main_form = "fused"
     f = forms[main_form]
+    cfg = cs.conv_get_tile_cfg(0, 0).as_dict()
     roofline = {
         "bound": "hbm",
-        "achieved": f["alg_GBps"],
+        "achieved": r3(f["alg_GBps"]),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": f["alg_GBps"] / HBM_PEAK_GBS,
+        "frac": r3(f["alg_GBps"] / HBM_PEAK_GBS),
         "traffic": traffic_for(main_form),
         "kernel": "k_image<F32, aligned, FUSED> ({rows_per_tile}-row bands, {waves_per_wg} wave(s) per "
-                  "workgroup, XCD chunks of {xcd_slabs} bands)".format(**cs.conv_get_tile_cfg(0, 0).as_dict()),
+                  "workgroup, XCD chunks of {xcd_slabs} bands)".format(**cfg),
         "alg_bytes_per_launch": f["alg_bytes_per_step"],
     }
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        cpu = cpu_baseline(oracle, np, host, k, args)
+        cpu = cpu_baseline(oracle, np, synth, host, k, args)
         progress("cpu baseline done")
+        for key in ("value", "one_core_mpix_per_s", "batch64_mpix_per_s", "batch64_one_core_mpix_per_s"):
+            cpu[key] = r3(cpu[key])
 
     line = {
         "metric": "MPix/s (3-plane) + % HBM roofline; serving p50/p99 latency vs per-image launch",
-        "value": f["mpix_per_s"],
+        "value": r3(f["mpix_per_s"]),
         "unit": "MPix/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -587,21 +786,33 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"one 3x{R}x{C} FP32 image, width-5 separable convolution, fused "
-                        "single-pass, 2-px border 0",
-            "planes": P, "rows": R, "cols": C,
-            "taps": "positive random, normalised to sum 1 (seed 2)",
-            "pixels": "uniform [0,1) (seed 1)",
+                        "single-pass, 2-px border 0 (uniform [0,1) pixels seed 1; positive random "
+                        "taps summing to 1, seed 2)",
             "buffer_sets_rotated": max(1, args.sets),
-            "tile_cfg": cs.conv_get_tile_cfg(0, 0).as_dict(),
+            "tile_cfg": cfg,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "forms": forms,
-        "fused_equals_2pass_bitwise": eq,
-        **extras,
-        "device": torch.cuda.get_device_name(0),
+        "summary": summarize(forms, extras, eq),
     }
-    print(json.dumps(line), flush=True)
+    detail = {"forms": forms, "fused_equals_2pass_bitwise": eq, **extras,
+              "device": torch.cuda.get_device_name(0), "headline": dict(line)}
+    detail["headline"].pop("summary")
+    text = json.dumps(detail)
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
+            fh.write(text + "\n")
+    else:
+        print("bench detail: " + text, file=sys.stderr, flush=True)
+    # the headline line stays short enough for a log tail: drop summary parts
+    # (they remain in the detail) until it fits
+    out = json.dumps(line)
+    for key in ("c5_640x480", "c4_us_per_image", "c1_us_per_call", "c5_mixed", "c3_batch64"):
+        if len(out) <= 4000:
+            break
+        line["summary"].pop(key, None)
+        out = json.dumps(line)
+    print(out, flush=True)
 
 
 if __name__ == "__main__":

@@ -46,6 +46,23 @@ conv_status conv_loadgen_direct(int32_t n, const double *arrival_s,
                                 int32_t n_streams, uint64_t *submit_ns,
                                 uint64_t *done_ns, double *lag_s);
 
+/* Launch-overhead probe, the GPU counterpart of the paper's empty tasks and
+ * empty OpenCL kernels (Section 6, Table 2): what one call costs apart from
+ * the pixels.  form 0 launches a kernel that does nothing (one wavefront);
+ * form 1 / 2 call conv_sep5_1pass (fused / direct 25-tap) and form 3
+ * conv_sep5_2pass on the image d_in -> d_out described by img, with taps
+ * k[0..4] and workspace d_tmp; form 0 reads none of them.  After one warm-up
+ * call the probe makes n calls back to back on `stream` between two timing
+ * events (gpu_us receives the elapsed time / n: the GPU's time per call with
+ * the launches queued ahead), then n calls one at a time, each followed by
+ * hipStreamSynchronize, timed on the host's steady clock (host_us receives
+ * the median: submit-to-completion latency of a lone call).  Synchronises
+ * `stream`.  n must be 1..100000; errors as conv_sep5_1pass / 2pass, or
+ * CONV_EHIP for the empty kernel's launch. */
+conv_status conv_loadgen_call_latency(int32_t form, int32_t n, const void *d_in, void *d_out,
+                                      float *d_tmp, const float *k, const conv_image *img,
+                                      hipStream_t stream, double *gpu_us, double *host_us);
+
 #ifdef __cplusplus
 }
 #endif

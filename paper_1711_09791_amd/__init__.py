@@ -148,7 +148,7 @@ def lib():
 
 _loadgen = None
 
-LOADGEN_EXPORTS = ("conv_loadgen_serve", "conv_loadgen_direct")
+LOADGEN_EXPORTS = ("conv_loadgen_serve", "conv_loadgen_direct", "conv_loadgen_call_latency")
 
 
 def loadgen_lib():
@@ -171,6 +171,9 @@ def loadgen_lib():
                                       ctypes.POINTER(ctypes.c_float), ctypes.POINTER(conv_image),
                                       i32, u64p, u64p, dp]
     G.conv_loadgen_direct.restype = ctypes.c_int
+    G.conv_loadgen_call_latency.argtypes = [i32, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(conv_image), vp, dp, dp]
+    G.conv_loadgen_call_latency.restype = ctypes.c_int
     _loadgen = G
     return G
 

@@ -3,6 +3,7 @@
 // calls libconvsep5 only through its public C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <mutex>
@@ -35,6 +36,21 @@ bool args_ok(int32_t n, const double *arr, const void *const *in, void *const *o
     if (n < 0) return false;
     if (n == 0) return true;
     return arr && in && out && k && imgs;
+}
+
+// A kernel with no work: what a launch costs by itself.
+__global__ void k_empty() {}
+
+conv_status one_call(int32_t form, const void *in, void *out, float *tmp, const float *k,
+                     const conv_image *img, hipStream_t s) {
+    switch (form) {
+        case 0:
+            hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s);
+            return hipGetLastError() == hipSuccess ? CONV_OK : CONV_EHIP;
+        case 1: return conv_sep5_1pass(in, out, k, img, CONV_1PASS_FUSED, s);
+        case 2: return conv_sep5_1pass(in, out, k, img, CONV_1PASS_DIRECT25, s);
+        default: return conv_sep5_2pass(in, out, tmp, k, img, s);
+    }
 }
 
 }  // namespace
@@ -113,6 +129,41 @@ conv_status conv_loadgen_direct(int32_t n, const double *arrival_s, const void *
         if (e) hipEventDestroy(e);
     for (auto s : streams)
         if (s) hipStreamDestroy(s);
+    return rc;
+}
+
+conv_status conv_loadgen_call_latency(int32_t form, int32_t n, const void *d_in, void *d_out,
+                                      float *d_tmp, const float *k, const conv_image *img,
+                                      hipStream_t stream, double *gpu_us, double *host_us) {
+    if (form < 0 || form > 3 || n < 1 || n > 100000 || !gpu_us || !host_us) return CONV_EINVAL;
+    if (form != 0 && (!d_in || !d_out || !k || !img)) return CONV_EINVAL;
+    conv_status rc = one_call(form, d_in, d_out, d_tmp, k, img, stream);
+    if (rc != CONV_OK) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = CONV_EHIP;
+    if (rc == CONV_OK && hipStreamSynchronize(stream) != hipSuccess) rc = CONV_EHIP;
+    if (rc == CONV_OK && hipEventRecord(e0, stream) != hipSuccess) rc = CONV_EHIP;
+    for (int32_t i = 0; i < n && rc == CONV_OK; ++i)
+        rc = one_call(form, d_in, d_out, d_tmp, k, img, stream);
+    if (rc == CONV_OK && hipEventRecord(e1, stream) != hipSuccess) rc = CONV_EHIP;
+    if (rc == CONV_OK && hipEventSynchronize(e1) != hipSuccess) rc = CONV_EHIP;
+    float ms = 0.f;
+    if (rc == CONV_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = CONV_EHIP;
+    if (rc == CONV_OK) *gpu_us = 1e3 * ms / n;
+    std::vector<double> lat;
+    lat.reserve(n);
+    for (int32_t i = 0; i < n && rc == CONV_OK; ++i) {
+        const auto t = Clock::now();
+        rc = one_call(form, d_in, d_out, d_tmp, k, img, stream);
+        if (rc == CONV_OK && hipStreamSynchronize(stream) != hipSuccess) rc = CONV_EHIP;
+        lat.push_back(std::chrono::duration<double, std::micro>(Clock::now() - t).count());
+    }
+    if (rc == CONV_OK) {
+        std::nth_element(lat.begin(), lat.begin() + n / 2, lat.end());
+        *host_us = lat[n / 2];
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
     return rc;
 }
 

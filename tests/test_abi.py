@@ -48,6 +48,13 @@ def test_loadgen_library_exports_its_header():
     # argument validation happens before any HIP call
     assert G.conv_loadgen_serve(None, 1, None, None, None, None, None, None, None, None) == cs.CONV_EINVAL
     assert G.conv_loadgen_direct(-1, None, None, None, None, None, 1, None, None, None) == cs.CONV_EINVAL
+    g, h = ctypes.c_double(), ctypes.c_double()
+    assert G.conv_loadgen_call_latency(4, 1, None, None, None, None, None, None, ctypes.byref(g),
+                                       ctypes.byref(h)) == cs.CONV_EINVAL
+    assert G.conv_loadgen_call_latency(0, 0, None, None, None, None, None, None, ctypes.byref(g),
+                                       ctypes.byref(h)) == cs.CONV_EINVAL
+    assert G.conv_loadgen_call_latency(1, 10, None, None, None, None, None, None, ctypes.byref(g),
+                                       ctypes.byref(h)) == cs.CONV_EINVAL
     assert G.conv_loadgen_direct(1, None, None, None, None, None, 0, None, None, None) == cs.CONV_EINVAL
 
 
