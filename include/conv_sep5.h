@@ -147,6 +147,31 @@ conv_status conv_sep5_2pass_ex(const void *d_in, void *d_out, void *d_tmp,
                                int32_t tmp_dtype, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the two-pass
+ * form of conv_sep5_2pass_ex with its intermediate held in a static device
+ * array of the library, CONV_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, which a
+ * GPU holds from the library's first use on it until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipMallocAsync, hipFree or allocating
+ * library routine) and computes exactly what conv_sep5_2pass_ex computes with
+ * a caller's workspace, bitwise.
+ *   d_in, d_out, k, img  as conv_sep5_2pass_ex (d_out == d_in allowed)
+ *   tmp_dtype    CONV_F32, CONV_F16 or CONV_BF16, as conv_sep5_2pass_ex
+ * An intermediate larger than the array (planes*rows*cols*4 bytes for
+ * CONV_F32, *2 for the 16-bit types; 128 MiB holds 3 x 3840 x 2160 in FP32)
+ * is CONV_ENOMEM, checked before any HIP call.  Every call on one GPU uses
+ * that GPU's one array, and the array keeps the last call's contents (the row
+ * pass writes every value the column pass reads, so nothing is cleared):
+ * calls ordered on one stream are safe; calls that can overlap on one GPU
+ * (different streams, or threads without stream ordering between them) race
+ * on the array and give wrong results.
+ */
+#define CONV_NOALLOC_SCRATCH_BYTES (128ull << 20)
+conv_status conv_sep5_2pass_noalloc(const void *d_in, void *d_out, const float k[5],
+                                    const conv_image *img, int32_t tmp_dtype,
+                                    hipStream_t stream);
+
+/*
  * Single-pass form (Section 5.1 and Section 7, "single-pass without
  * copy-back": the result is written once to a separate output).  One kernel;
  * mode CONV_1PASS_FUSED keeps the row-filtered rows in registers, mode

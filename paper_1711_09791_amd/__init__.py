@@ -24,6 +24,8 @@ CONV_OK, CONV_EINVAL, CONV_EALIAS, CONV_ENOMEM = 0, -1, -2, -3
 CONV_EHIP, CONV_EAGAIN, CONV_ENOTFOUND = -4, -5, -6
 CONV_F32, CONV_F16, CONV_BF16 = 0, 1, 2
 CONV_1PASS_FUSED, CONV_1PASS_DIRECT25 = 0, 1
+# bytes of the static device workspace of conv_sep5_2pass_noalloc (per GPU)
+CONV_NOALLOC_SCRATCH_BYTES = 128 << 20
 KIND_IMAGE, KIND_BATCH = 0, 1
 
 _STATUS_NAMES = {0: "CONV_OK", -1: "CONV_EINVAL", -2: "CONV_EALIAS", -3: "CONV_ENOMEM",
@@ -81,7 +83,8 @@ class ConvError(RuntimeError):
 _lib = None
 
 EXPORTS = (
-    "conv_sep5_2pass", "conv_sep5_2pass_ex", "conv_sep5_1pass", "conv_image_copy",
+    "conv_sep5_2pass", "conv_sep5_2pass_ex", "conv_sep5_2pass_noalloc", "conv_sep5_1pass",
+    "conv_image_copy",
     "conv_sep5_batch",
     "conv_batch_plan_create", "conv_batch_plan_launch", "conv_batch_plan_destroy",
     "conv_sepn_1pass", "conv_sepn_2pass", "conv_2d_direct", "conv_pyr_down",
@@ -109,6 +112,7 @@ def lib():
     sig = {
         "conv_sep5_2pass": [vp, vp, vp, fp, imgp, vp],
         "conv_sep5_2pass_ex": [vp, vp, vp, fp, imgp, i32, vp],
+        "conv_sep5_2pass_noalloc": [vp, vp, fp, imgp, i32, vp],
         "conv_sep5_1pass": [vp, vp, fp, imgp, ctypes.c_int, vp],
         "conv_image_copy": [vp, vp, imgp, vp],
         "conv_sep5_batch": [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, imgp, ctypes.c_int, vp],
@@ -343,6 +347,18 @@ def conv_sep5_2pass_ex(d_in, d_out, k, tmp_dtype: int, d_tmp=None,
         _check_workspace(d_tmp, img, 4 if int(tmp_dtype) == CONV_F32 else 2)
     return _check(lib().conv_sep5_2pass_ex(_ptr(d_in), _ptr(d_out), _ptr(d_tmp), _taps(k),
                                            ctypes.byref(img), int(tmp_dtype), _stream(stream)))
+
+
+def conv_sep5_2pass_noalloc(d_in, d_out, k, tmp_dtype: int = CONV_F32,
+                            img: conv_image | None = None, stream=None):
+    """Two-pass form with the intermediate in the library's static device
+    workspace (CONV_NOALLOC_SCRATCH_BYTES per GPU): allocates nothing.  Calls
+    that can overlap on one GPU race on that workspace."""
+    if img is None:
+        _same_layout(d_in, d_out)
+        img = image_of(d_in)
+    return _check(lib().conv_sep5_2pass_noalloc(_ptr(d_in), _ptr(d_out), _taps(k), ctypes.byref(img),
+                                                int(tmp_dtype), _stream(stream)))
 
 
 def conv_sep5_1pass(d_in, d_out, k, mode: int = CONV_1PASS_FUSED,

@@ -666,6 +666,62 @@ conv_status conv_sep5_2pass(const void *d_in, void *d_out, float *d_tmp, const f
     return twopass(d_in, d_out, d_tmp, k, img, CONV_F32, stream);
 }
 
+// ---- the two-pass without allocation ----------------------------------------------
+// The intermediate of conv_sep5_2pass_noalloc lives in this array: every GPU that
+// loads the library's code object holds its own copy, at its own address, until the
+// process ends.  In host code the name is only a stand-in for the symbol; its
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[CONV_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+// The current device's copy of `scratch` (looked up on its first use on that device).
+static conv_status scratch_of_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_error(CONV_EINVAL, "device %d: the static workspace serves devices 0..%d", dev,
+                         kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(CONV_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CONV_OK;
+}
+
+conv_status conv_sep5_2pass_noalloc(const void *d_in, void *d_out, const float k[5],
+                                    const conv_image *img, int32_t tmp_dtype,
+                                    hipStream_t stream) {
+    clear_error();
+    Layout L;
+    conv_status st = check_image(img, &L);
+    if (st != CONV_OK) return st;
+    if (tmp_dtype != CONV_F32 && tmp_dtype != CONV_F16 && tmp_dtype != CONV_BF16)
+        return set_error(CONV_EINVAL, "tmp_dtype %d is not CONV_F32, CONV_F16 or CONV_BF16",
+                         tmp_dtype);
+    const uint64_t tmp_bytes =
+        (uint64_t)img->planes * img->rows * img->cols * (tmp_dtype == CONV_F32 ? 4 : 2);
+    if (tmp_bytes > CONV_NOALLOC_SCRATCH_BYTES)
+        return set_error(CONV_ENOMEM,
+                         "the intermediate takes %llu bytes, more than the %llu-byte static "
+                         "workspace of conv_sep5_2pass_noalloc",
+                         (unsigned long long)tmp_bytes,
+                         (unsigned long long)CONV_NOALLOC_SCRATCH_BYTES);
+    if (L.empty) return CONV_OK;
+    void *tmp = nullptr;
+    st = scratch_of_current_device(&tmp);
+    if (st != CONV_OK) return st;
+    return twopass(d_in, d_out, tmp, k, img, tmp_dtype, stream);
+}
+
 conv_status conv_sep5_2pass_ex(const void *d_in, void *d_out, void *d_tmp, const float k[5],
                                const conv_image *img, int32_t tmp_dtype, hipStream_t stream) {
     return twopass(d_in, d_out, d_tmp, k, img, tmp_dtype, stream);

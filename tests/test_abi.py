@@ -475,3 +475,23 @@ def test_tuner_cache_rejects_bad_files(tmp_path, bad):
     assert not cs.conv_get_tile_cfg_for(0, 1, 2 << 30)[1]
     assert L.conv_tune_load(os.fsencode(str(tmp_path / "missing.json"))) == cs.CONV_ENOTFOUND
     assert L.conv_tune_load(None) == cs.CONV_EINVAL
+
+
+def test_noalloc_rejects_what_does_not_fit_before_any_hip_call():
+    L = cs.lib()
+    kk = (ctypes.c_float * 5)(0.1, 0.2, 0.4, 0.2, 0.1)
+    dummy_in, dummy_out = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000000000)
+    # 3 x 4096 x 4096 FP32 intermediate = 192 MiB > 128 MiB
+    big = conv_image(3, 4096, 4096, cs.CONV_F32, 0, 0)
+    assert L.conv_sep5_2pass_noalloc(dummy_in, dummy_out, kk, ctypes.byref(big), cs.CONV_F32,
+                                     None) == cs.CONV_ENOMEM
+    assert "static" in cs.conv_last_error()
+    # one byte over, 16-bit intermediate: 2 * planes * rows * cols = 128 MiB + 2
+    over = conv_image(1, 1, (cs.CONV_NOALLOC_SCRATCH_BYTES // 2) + 1, cs.CONV_F32, 0, 0)
+    assert L.conv_sep5_2pass_noalloc(dummy_in, dummy_out, kk, ctypes.byref(over), cs.CONV_F16,
+                                     None) == cs.CONV_ENOMEM
+    assert L.conv_sep5_2pass_noalloc(dummy_in, dummy_out, kk, ctypes.byref(big), 7,
+                                     None) == cs.CONV_EINVAL
+    # nothing to do: no HIP call, no error
+    empty = conv_image(3, 0, 4096, cs.CONV_F32, 0, 0)
+    assert L.conv_sep5_2pass_noalloc(None, None, kk, ctypes.byref(empty), cs.CONV_F32, None) == cs.CONV_OK
