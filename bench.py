@@ -24,9 +24,11 @@ to --detail-out, or to one stderr line):
              as a captured graph), with the default and the autotuned tile
              configuration, against one launch per image;
   serving    Poisson arrivals of 640x480 .. 3840x2160 frames, each with its
-             own taps: p50/p99 latency of the continuous-batching server
+             own taps: p50/p99 latency (from each request's scheduled
+             arrival to its completion) of the continuous-batching server
              against one launch per request (1 or 4 streams), at 0.5x and
-             0.8x of the batched server's measured capacity; and 640x480 only;
+             0.8x of the batched server's measured capacity, median of three
+             interleaved repetitions; and 640x480 only;
   widths     odd widths n = 1..9 on the same image: fused, two-pass and
              direct (n*n terms) separable forms and a full non-separable
              n x n kernel, each against the HBM and the FP32 ALU roofline
@@ -82,6 +84,8 @@ def parse():
                     help="write every figure as JSON to this file (default: one line on stderr)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-reps", type=int, default=3,
+                    help="repetitions of each serving point (medians reported)")
     ap.add_argument("--cpu-min-s", type=float, default=10.0,
                     help="repeat the oracle until this much CPU time is spent")
     return ap.parse_args()
@@ -504,10 +508,16 @@ def bench_serving(torch, cs, synth, args, sizes=None):
     q = lambda v, p: v[min(len(v) - 1, int(p * len(v)))]  # noqa: E731
 
     def summarize(sub, done, lag, n, warm, rate, extra):
-        lat = sorted((d - s) / 1e3 for s, d in zip(sub[warm:], done[warm:]))
+        # latency from the request's scheduled arrival: the time from submit to
+        # done plus how late the load generator submitted it (a submitting
+        # thread that is still busy launching the previous request delays the
+        # next one; that wait belongs to the request's latency)
+        lat = sorted((d - s) / 1e3 + lg * 1e6 for s, d, lg in zip(sub[warm:], done[warm:], lag[warm:]))
+        lat_sub = sorted((d - s) / 1e3 for s, d in zip(sub[warm:], done[warm:]))
         span = (max(done[warm:]) - min(sub[warm:])) / 1e9
         lg = sorted(lag)
         return {"p50_us": q(lat, 0.50), "p99_us": q(lat, 0.99), "mean_us": sum(lat) / len(lat),
+                "p50_from_submit_us": q(lat_sub, 0.50), "p99_from_submit_us": q(lat_sub, 0.99),
                 "throughput_req_per_s": (n - warm) / span, "offered_req_per_s": rate,
                 "submit_lag_p99_us": q(lg, 0.99) * 1e6, **extra}
 
@@ -544,13 +554,17 @@ def bench_serving(torch, cs, synth, args, sizes=None):
         return summarize(list(sub), list(done), list(lag), n, warm, rate, {"launches": n})
 
     MB = 1 << 20
+    # "batched" is the server as recommended: every launch made by its
+    # scheduler thread, so one thread makes all HIP calls (measured faster
+    # than letting the submitting thread launch, whose launch calls then
+    # contend with the scheduler's event polling in the HIP runtime)
     policies = {
-        "batched": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm),
-        "batched_8_streams": lambda rate, n, warm: run_server(16, 8, 128 * MB, rate, n, warm),
-        "batched_count_cap_only": lambda rate, n, warm: run_server(16, 4, 0, rate, n, warm),
-        # every launch made by the scheduler thread (no launches from submit)
-        "batched_queue_only": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm,
-                                                               queue_only=True),
+        "batched": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm, queue_only=True),
+        "batched_submit_launch": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm),
+        "batched_8_streams": lambda rate, n, warm: run_server(16, 8, 128 * MB, rate, n, warm,
+                                                              queue_only=True),
+        "batched_count_cap_only": lambda rate, n, warm: run_server(16, 4, 0, rate, n, warm,
+                                                                   queue_only=True),
         "per_image_launch": lambda rate, n, warm: run_direct(1, rate, n, warm),
         "per_image_launch_4_streams": lambda rate, n, warm: run_direct(4, rate, n, warm),
     }
@@ -558,14 +572,30 @@ def bench_serving(torch, cs, synth, args, sizes=None):
     capacity = caps["batched"]
     out = {"capacity_req_per_s": caps,
            "batched_policy": {"max_batch": 16, "streams": 4, "max_slots": NBUF,
-                              "max_batch_bytes": 128 * MB, "hbm_budget_bytes": budget},
-           "sizes": [f"3x{h}x{w}" for (h, w) in sizes], "levels": {}}
+                              "max_batch_bytes": 128 * MB, "hbm_budget_bytes": budget,
+                              "launches": "scheduler thread only"},
+           "sizes": [f"3x{h}x{w}" for (h, w) in sizes], "reps": args.serve_reps, "levels": {}}
     n = args.serve_requests + args.serve_warmup
+    names = list(policies)
+    med = lambda v: sorted(v)[len(v) // 2]  # noqa: E731
     for frac in (0.5, 0.8):
         lam = frac * capacity
+        runs = {name: [] for name in names}
+        # the policies take turns, in a rotated order each repetition, so that a
+        # drift of the machine during the measurement falls on all of them
+        for rep in range(max(1, args.serve_reps)):
+            for j in range(len(names)):
+                name = names[(j + rep) % len(names)]
+                runs[name].append(policies[name](lam, n, args.serve_warmup))
         lvl = {"rate_req_per_s": lam}
-        for name, fn in policies.items():
-            lvl[name] = fn(lam, n, args.serve_warmup)
+        for name, rs in runs.items():
+            r = dict(rs[len(rs) // 2])  # stage times and counters of one repetition
+            r.update({"p50_us": med([x["p50_us"] for x in rs]), "p99_us": med([x["p99_us"] for x in rs]),
+                      "mean_us": med([x["mean_us"] for x in rs]),
+                      "p50_from_submit_us": med([x["p50_from_submit_us"] for x in rs]),
+                      "p99_from_submit_us": med([x["p99_from_submit_us"] for x in rs]),
+                      "per_rep_p50_p99_us": [[x["p50_us"], x["p99_us"]] for x in rs]})
+            lvl[name] = r
         out["levels"][f"{frac:.1f}x_batched_capacity"] = lvl
     return out
 

@@ -396,6 +396,15 @@ conv_status conv_tune_load(const char *path);
  * completes.  Requests that arrive while others run are admitted into
  * the next launch, on another stream, so their work overlaps on the device.
  * Each result is bitwise identical to a lone conv_sep5_1pass (fused) call.
+ * The queue is host memory (request descriptors); the images stay in device
+ * memory throughout.
+ * Ordering: requests whose buffers overlap run in submission order.  A
+ * request that reads bytes an earlier, not yet completed request writes, or
+ * writes bytes such a request reads or writes (a chained pair: B's input is
+ * A's output; a shared output), is not admitted until that earlier request
+ * has completed, and never shares its launch; admission waits for it (later
+ * requests queue behind it).  A request's own input and output must not
+ * overlap (CONV_EALIAS at submit).
  */
 typedef struct {
     uint64_t hbm_budget_bytes; /* max sum of footprints in flight (> 0)      */
@@ -410,10 +419,12 @@ typedef struct {
                                   conv_serve_submit); 0: the caller promises
                                   every input is complete when it submits  */
     int32_t queue_only;        /* 0: a submit that finds nothing queued and
-                                  a stream idle, >= 10 us after the previous
-                                  submit, launches its request itself (the
-                                  scheduler retires it); dense arrivals go
-                                  to the scheduler, which batches them;
+                                  a stream idle launches its request itself
+                                  (the scheduler retires it) while submits
+                                  are sparse (running mean gap >= 8 us,
+                                  about one launch's enqueue time); dense
+                                  arrivals go to the scheduler, which
+                                  batches them;
                                   1: every launch is made by the scheduler */
 } conv_serve_cfg;
 

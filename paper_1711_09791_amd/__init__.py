@@ -527,7 +527,7 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                  max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                 producer_wait: bool = True, queue_only: bool = False):
+                 producer_wait: bool = True, queue_only: bool = True):
         cfg = conv_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(n_streams),
                              int(max_batch), int(device), int(max_batch_bytes),
                              int(bool(producer_wait)), int(bool(queue_only)))
@@ -577,7 +577,7 @@ class Server:
 
 def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                       max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                      producer_wait: bool = True, queue_only: bool = False) -> Server:
+                      producer_wait: bool = True, queue_only: bool = True) -> Server:
     return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device, max_batch_bytes,
                   producer_wait, queue_only)
 

@@ -2,33 +2,43 @@
 // convolution.
 //
 // Requests (device-resident images of any size, each with its own taps) are
-// submitted without blocking.  One scheduler thread per server loops over:
+// submitted without blocking into a host-side queue; the images stay in
+// device memory and only their descriptors pass through the queue.  One
+// scheduler thread per server loops over:
 //   1. retire: launches whose completion event has fired free their slots and
 //      HBM budget and stamp their tickets done;
 //   2. admit: while a launch stream is idle, queued requests are taken in
 //      arrival order as long as a slot is free and their footprint (input +
 //      output bytes) fits the budget, up to max_batch requests of one dtype
 //      and max_batch_bytes per launch (so large frames run alone and small
-//      ones share launches);
+//      ones share launches).  A request whose buffers overlap those of a
+//      request admitted before it and not yet retired (it reads what that one
+//      writes, or writes what that one reads or writes) stops admission until
+//      that request retires, so such requests run in submission order and
+//      never share a launch;
 //   3. launch: each admitted group becomes ONE batch launch on its stream (a
 //      group of one the single-image kernel), after a wait on the producers'
 //      events, followed by a completion event;
-//   4. poll the in-flight events, or spin briefly and then sleep when idle;
-//      while nothing was submitted or finished the loop skips the lock.
-// A submit that finds nothing queued and a stream idle, arriving at least
-// 10 us after the previous one, launches its request itself (unless
-// queue_only is set): at sparse arrivals there is nothing to batch with and
-// the hop to the scheduler only adds latency.  It hands the in-flight launch
-// to the scheduler, which retires it like its own.
+//   4. poll the in-flight events without pausing, or spin 2 ms and then
+//      sleep when idle; while nothing was submitted or finished the loop
+//      skips the lock.
+// A submit that finds nothing queued and a stream idle launches its request
+// itself (unless queue_only is set) when submits arrive sparsely: the running
+// mean gap between submits is at least the time a launch takes to enqueue,
+// so there is nothing to batch with and the hop to the scheduler would only
+// add latency.  It hands the in-flight launch to the scheduler, which retires
+// it like its own.  Dense arrivals go to the scheduler, which batches them.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
 // same tile code on the same values as a lone call, so it is bitwise
 // identical.
 //
 // Locking: the mutex guards what submitters and pollers touch (queue, ticket
-// table, event pool, statistics) and the budget counters.  Streams and the
-// list of in-flight launches belong to the scheduler thread, and every HIP
-// call of the scheduler runs without the lock.
+// table, request pool, event pool, statistics) and the budget counters.
+// Streams and the list of in-flight launches belong to the scheduler thread,
+// and every HIP call of the scheduler runs without the lock.  Requests live in
+// a pool of fixed blocks and are found by ticket in a power-of-two table, so
+// a submit or a poll allocates nothing once the pool has warmed up.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,8 +47,8 @@
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <memory>
 #include <thread>
-#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -57,22 +67,38 @@ uint64_t now_ns() {
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3 };
 
 constexpr uint64_t kSpinIdleNs = 2000000;  // scheduler spins 2 ms after going idle
-// A submit launches its request itself only if the previous submit was at
-// least this long ago (longer than a launch takes to enqueue).
-constexpr uint64_t kDirectGapNs = 10000;
+// A submit launches its request itself only while the running mean gap
+// between submits is at least this long (about what a launch takes to
+// enqueue): then the submitting thread keeps up with its arrivals.
+constexpr uint64_t kDirectGapNs = 8000;
+// The running mean: gap_mean += (gap - gap_mean) / 4, each gap clamped to
+// kGapClampNs so that a burst after an idle spell is seen within a few submits.
+constexpr uint64_t kGapClampNs = 100000;
+constexpr int kPoolBlock = 256;         // requests per pool block
+constexpr size_t kTicketTable0 = 1024;  // initial ticket table size (power of two)
 
 struct Req {
     uint64_t ticket = 0;
     const void *in = nullptr;
     void *out = nullptr;
+    int64_t bytes = 0;           // extent of the input (and of the output) in bytes
     float k[5] = {0, 0, 0, 0, 0};
     conv_image img{};
     uint64_t footprint = 0;
     conv_req_times t{};
     int state = QUEUED;
+    int active_idx = -1;         // position in the server's admitted list
     hipEvent_t ready = nullptr;  // recorded on the producer stream at submit
     hipStream_t producer = nullptr;
 };
+
+// Whether b, submitted after a, must wait for a: b reads what a writes, or
+// writes what a reads or writes.
+bool conflicts(const Req *a, const Req *b) {
+    return overlaps(b->in, b->bytes, a->out, a->bytes) ||
+           overlaps(b->out, b->bytes, a->in, a->bytes) ||
+           overlaps(b->out, b->bytes, a->out, a->bytes);
+}
 
 struct Launch {
     std::vector<Req *> reqs;
@@ -95,12 +121,17 @@ struct conv_server {
     std::condition_variable cv;       // new work or stop
     std::condition_variable idle_cv;  // nothing queued or in flight
     std::deque<Req *> queue;
-    std::unordered_map<uint64_t, Req *> reqs;
+    std::vector<Req *> active;           // admitted, not yet retired
+    // requests: fixed blocks, a free list, and the ticket table
+    std::vector<std::unique_ptr<Req[]>> blocks;
+    std::vector<Req *> free_reqs;
+    std::vector<Req *> table;            // ticket & (size - 1) -> live request
     std::vector<hipEvent_t> ready_pool;  // producer-stream events
     std::vector<hipEvent_t> event_pool;  // launch-completion events
     std::vector<char> stream_busy;
     std::vector<Launch> handoff;         // launched by a submitter, not yet polled
     uint64_t last_submit_ns = 0;
+    uint64_t gap_mean_ns = kGapClampNs;  // running mean gap between submits
     uint64_t bytes_in_flight = 0;
     int slots_in_flight = 0;
     uint64_t next_ticket = 1;
@@ -115,9 +146,87 @@ struct conv_server {
 
     void run();
     std::vector<Launch> admit_locked();
+    bool blocked_locked(const Req *r, const Launch &L) const;
+    void retire_locked(Req *r, int state, uint64_t t_done);
     conv_status enqueue(Launch &L, hipEvent_t done_ev);
     bool launched_locked(Launch &L, conv_status rc, uint64_t t_launch);
+    Req *new_req_locked();
+    void put_ticket_locked(Req *r);
+    Req *find_ticket_locked(uint64_t ticket) const;
+    void free_req_locked(Req *r);
 };
+
+Req *conv_server::new_req_locked() {
+    if (free_reqs.empty()) {
+        blocks.emplace_back(new Req[kPoolBlock]);
+        Req *b = blocks.back().get();
+        free_reqs.reserve(blocks.size() * kPoolBlock);
+        for (int i = kPoolBlock - 1; i >= 0; --i) free_reqs.push_back(&b[i]);
+    }
+    Req *r = free_reqs.back();
+    free_reqs.pop_back();
+    *r = Req();
+    return r;
+}
+
+// Tickets are consecutive, so live tickets collide in the table only when
+// more of them are unpolled than it has entries: then it doubles.
+void conv_server::put_ticket_locked(Req *r) {
+    if (table.empty()) table.assign(kTicketTable0, nullptr);
+    while (table[r->ticket & (table.size() - 1)]) {
+        std::vector<Req *> old;
+        old.swap(table);
+        for (size_t n = old.size() * 2;; n *= 2) {
+            table.assign(n, nullptr);
+            bool ok = true;
+            for (Req *e : old) {
+                if (!e) continue;
+                Req *&slot = table[e->ticket & (n - 1)];
+                if (slot) {
+                    ok = false;
+                    break;
+                }
+                slot = e;
+            }
+            if (ok) break;
+        }
+    }
+    table[r->ticket & (table.size() - 1)] = r;
+}
+
+Req *conv_server::find_ticket_locked(uint64_t ticket) const {
+    if (table.empty()) return nullptr;
+    Req *r = table[ticket & (table.size() - 1)];
+    return r && r->ticket == ticket ? r : nullptr;
+}
+
+void conv_server::free_req_locked(Req *r) {
+    table[r->ticket & (table.size() - 1)] = nullptr;
+    free_reqs.push_back(r);
+}
+
+// The request leaves the admitted list with its final state.
+void conv_server::retire_locked(Req *r, int state, uint64_t t_done) {
+    r->t.done_ns = t_done;
+    r->state = state;
+    if (r->active_idx >= 0) {
+        Req *last = active.back();
+        active[r->active_idx] = last;
+        last->active_idx = r->active_idx;
+        active.pop_back();
+        r->active_idx = -1;
+    }
+}
+
+// r must wait: it conflicts with an admitted request not yet retired, or with
+// one already in the group being formed.
+bool conv_server::blocked_locked(const Req *r, const Launch &L) const {
+    for (const Req *a : active)
+        if (conflicts(a, r)) return true;
+    for (const Req *a : L.reqs)
+        if (conflicts(a, r)) return true;
+    return false;
+}
 
 // Takes admissible requests off the queue (caller holds mu).
 std::vector<Launch> conv_server::admit_locked() {
@@ -138,7 +247,8 @@ std::vector<Launch> conv_server::admit_locked() {
                slots_in_flight + 1 <= cfg.max_slots &&
                bytes_in_flight + queue.front()->footprint <= cfg.hbm_budget_bytes &&
                queue.front()->img.dtype == dtype &&
-               (L.reqs.empty() || L.bytes + queue.front()->footprint <= cap)) {
+               (L.reqs.empty() || L.bytes + queue.front()->footprint <= cap) &&
+               !blocked_locked(queue.front(), L)) {
             Req *r = queue.front();
             queue.pop_front();
             L.reqs.push_back(r);
@@ -146,7 +256,9 @@ std::vector<Launch> conv_server::admit_locked() {
             bytes_in_flight += r->footprint;
             slots_in_flight += 1;
         }
-        if (L.reqs.empty()) break;  // the head does not fit yet: wait for a retirement
+        // the head does not fit yet, or must wait for an earlier request:
+        // wait for a retirement
+        if (L.reqs.empty()) break;
         stream_busy[s] = 1;
         const uint64_t t = now_ns();
         for (Req *r : L.reqs) {
@@ -154,6 +266,8 @@ std::vector<Launch> conv_server::admit_locked() {
             r->t.batch_size = (int32_t)L.reqs.size();
             r->t.stream = s;
             r->state = INFLIGHT;
+            r->active_idx = (int)active.size();
+            active.push_back(r);
         }
         if (event_pool.empty()) {
             hipEvent_t e = nullptr;
@@ -176,6 +290,16 @@ std::vector<Launch> conv_server::admit_locked() {
 conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     if (!done_ev) return CONV_EHIP;
     const int n = (int)L.reqs.size();
+    hipStream_t s = streams[L.stream];
+    if (n == 1) {
+        // a group of one runs the single-image kernel (same tiles, same bits)
+        const Req *r = L.reqs[0];
+        conv_status st = CONV_OK;
+        if (r->ready && hipStreamWaitEvent(s, r->ready, 0) != hipSuccess) st = CONV_EHIP;
+        if (st == CONV_OK) st = conv_sep5_1pass(r->in, r->out, r->k, &r->img, CONV_1PASS_FUSED, s);
+        if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
+        return st;
+    }
     const int dtype = L.reqs[0]->img.dtype;
     std::vector<const void *> ins(n);
     std::vector<void *> outs(n);
@@ -188,16 +312,12 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
         for (int j = 0; j < 5; ++j) ks[5 * i + j] = r->k[j];
         imgs[i] = r->img;
     }
-    hipStream_t s = streams[L.stream];
     const conv_tile_cfg tc = get_cfg(dtype, 1);
     std::vector<ImgDev> descs;
     int64_t total = 0;
     int dt = 0;
-    // a group of one runs the single-image kernel (same tiles, same bits,
-    // less to marshal); larger groups one batch launch
-    conv_status st = n == 1 ? CONV_OK
-                            : build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
-                                          CONV_1PASS_FUSED, tc, &descs, &total, &dt);
+    conv_status st = build_batch(n, ins.data(), outs.data(), ks.data(), imgs.data(),
+                                 CONV_1PASS_FUSED, tc, &descs, &total, &dt);
     // The launch starts only after each request's producer work.  Events
     // recorded on one stream complete in order, so waiting on the latest
     // request of each producer stream covers the earlier ones.
@@ -214,9 +334,7 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     }
     for (auto &pe : last)
         if (st == CONV_OK && hipStreamWaitEvent(s, pe.second, 0) != hipSuccess) st = CONV_EHIP;
-    if (st == CONV_OK)
-        st = n == 1 ? conv_sep5_1pass(ins[0], outs[0], ks.data(), &imgs[0], CONV_1PASS_FUSED, s)
-                    : enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
+    if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
     if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
     return st;
 }
@@ -231,10 +349,7 @@ bool conv_server::launched_locked(Launch &L, conv_status rc, uint64_t t_launch) 
         r->t.launch_ns = t_launch;
     }
     if (rc != CONV_OK) {
-        for (Req *r : L.reqs) {
-            r->t.done_ns = t_launch;
-            r->state = FAILED;
-        }
+        for (Req *r : L.reqs) retire_locked(r, FAILED, t_launch);
         stats.failed += L.reqs.size();
         bytes_in_flight -= L.bytes;
         slots_in_flight -= (int)L.reqs.size();
@@ -268,20 +383,14 @@ void conv_server::run() {
         // Nothing finished and nothing submitted since the last look: the
         // queue cannot have become admissible, so poll again without mu.
         const uint64_t s_now = seq.load(std::memory_order_acquire);
-        if (finished.empty() && s_now == seen && !inflight.empty()) {
-            std::this_thread::yield();
-            continue;
-        }
+        if (finished.empty() && s_now == seen && !inflight.empty()) continue;
         seen = s_now;
         std::vector<Launch> admitted;
         {
             std::lock_guard<std::mutex> g(mu);
             for (auto &fq : finished) {
                 Launch &L = fq.first;
-                for (Req *r : L.reqs) {
-                    r->t.done_ns = t_done;
-                    r->state = fq.second == hipSuccess ? DONE : FAILED;
-                }
+                for (Req *r : L.reqs) retire_locked(r, fq.second == hipSuccess ? DONE : FAILED, t_done);
                 if (fq.second == hipSuccess) stats.completed += L.reqs.size();
                 else stats.failed += L.reqs.size();
                 bytes_in_flight -= L.bytes;
@@ -305,11 +414,10 @@ void conv_server::run() {
                 if (launched_locked(admitted[i], rc[i], t_launch))
                     inflight.push_back(std::move(admitted[i]));
         }
-        // 4. wait
-        if (!inflight.empty()) {
-            std::this_thread::yield();
-            continue;
-        }
+        // 4. wait: while launches are in flight the thread polls without
+        // pausing (a yield costs a system call and delays the next admission
+        // and retirement by a few microseconds, measured)
+        if (!inflight.empty()) continue;
         std::unique_lock<std::mutex> lk(mu);
         // (slots still in flight here belong to a launch a submitter is making)
         if (!queue.empty() || !handoff.empty() || slots_in_flight > 0) continue;
@@ -321,8 +429,8 @@ void conv_server::run() {
         const uint64_t idle_from = now_ns();
         const uint64_t s_idle = seq.load(std::memory_order_relaxed);
         lk.unlock();
-        while (seq.load(std::memory_order_acquire) == s_idle && now_ns() - idle_from < kSpinIdleNs)
-            std::this_thread::yield();
+        while (seq.load(std::memory_order_acquire) == s_idle && now_ns() - idle_from < kSpinIdleNs) {
+        }
         lk.lock();
         if (queue.empty() && handoff.empty() && !stop) cv.wait(lk);
     }
@@ -403,15 +511,6 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             return hip_error(e, "recording the request's ready event");
         }
     }
-    auto *r = new Req();
-    r->ready = ready;
-    r->producer = stream;
-    r->in = d_in;
-    r->out = d_out;
-    for (int i = 0; i < 5; ++i) r->k[i] = k[i];
-    r->img = *img;
-    r->footprint = fp;
-    r->t.submit_ns = t_submit;
     // the direct launch runs on this thread: its current device must be the
     // server's (descriptors and the CU count follow the current device)
     int cur = -1;
@@ -421,26 +520,37 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
     {
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->stop) {
-            if (r->ready) srv->ready_pool.push_back(r->ready);
-            delete r;
+            if (ready) srv->ready_pool.push_back(ready);
             return set_error(CONV_EINVAL, "server is shutting down");
         }
+        Req *r = srv->new_req_locked();
+        r->ready = ready;
+        r->producer = stream;
+        r->in = d_in;
+        r->out = d_out;
+        r->bytes = L.extent_bytes;
+        for (int i = 0; i < 5; ++i) r->k[i] = k[i];
+        r->img = *img;
+        r->footprint = fp;
+        r->t.submit_ns = t_submit;
         r->ticket = srv->next_ticket++;
+        srv->put_ticket_locked(r);
         srv->stats.submitted += 1;
-        srv->reqs[r->ticket] = r;
         if (L.empty) {
             r->t.admit_ns = r->t.launch_ns = r->t.done_ns = r->t.submit_ns;
             r->state = DONE;
             srv->stats.completed += 1;
         } else {
-            // Nothing is queued and the previous request came long enough ago
-            // that this thread can spend a launch (~6 us) without falling
-            // behind its arrivals: there is nothing to batch this request
-            // with, so admit and launch it here (if a stream is idle) rather
-            // than wake the scheduler.  Dense arrivals stay with the
-            // scheduler, which batches them.
+            // Nothing is queued and submits arrive sparsely enough that this
+            // thread can spend a launch (~5 us) without falling behind its
+            // arrivals: there is nothing to batch this request with, so admit
+            // and launch it here (if a stream is idle and no earlier request
+            // holds its buffers) rather than wake the scheduler.  Dense
+            // arrivals stay with the scheduler, which batches them.
+            const uint64_t gap = std::min<uint64_t>(t_submit - srv->last_submit_ns, kGapClampNs);
+            srv->gap_mean_ns = srv->gap_mean_ns - srv->gap_mean_ns / 4 + gap / 4;
             const bool try_direct = !srv->cfg.queue_only && srv->queue.empty() &&
-                                    t_submit - srv->last_submit_ns >= kDirectGapNs;
+                                    srv->gap_mean_ns >= kDirectGapNs;
             srv->last_submit_ns = t_submit;
             srv->queue.push_back(r);
             srv->idle = false;
@@ -473,15 +583,12 @@ conv_status conv_serve_poll(conv_server *srv, uint64_t ticket, conv_req_times *t
     clear_error();
     if (!srv) return set_error(CONV_EINVAL, "NULL server");
     std::lock_guard<std::mutex> g(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end())
-        return set_error(CONV_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-    Req *r = it->second;
+    Req *r = srv->find_ticket_locked(ticket);
+    if (!r) return set_error(CONV_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
     if (r->state == QUEUED || r->state == INFLIGHT) return CONV_EAGAIN;
     if (t) *t = r->t;
     const int state = r->state;
-    srv->reqs.erase(it);
-    delete r;
+    srv->free_req_locked(r);
     if (state == FAILED)
         return set_error(CONV_EHIP, "the launch of ticket %llu failed", (unsigned long long)ticket);
     return CONV_OK;
@@ -521,8 +628,7 @@ conv_status conv_serve_destroy(conv_server *srv) {
     for (hipEvent_t e : srv->ready_pool) hipEventDestroy(e);
     for (hipStream_t s : srv->streams) hipStreamDestroy(s);
     hipSetDevice(prev);
-    for (auto &kv : srv->reqs) delete kv.second;
-    delete srv;
+    delete srv;  // the request pool's blocks go with it
     return CONV_OK;
 }
 

@@ -222,7 +222,7 @@ def test_drain_sees_direct_launches():
     report idle while a submitter is still launching)."""
     import torch
 
-    srv = cs.conv_serve_create(1 << 30, max_slots=8, n_streams=2, max_batch=4)
+    srv = cs.conv_serve_create(1 << 30, max_slots=8, n_streams=2, max_batch=4, queue_only=False)
     try:
         for i in range(60):
             a = torch.rand(3, 96 + i, 130, device="cuda")
@@ -303,3 +303,75 @@ def test_no_producer_wait_mode_after_sync():
         r = gu.nan_like(a)
         cs.conv_sep5_1pass(a, r, k)
         assert torch.equal(o, r)
+
+
+@pytest.mark.parametrize("queue_only", [False, True])
+def test_overlapping_requests_run_in_submission_order(queue_only):
+    """Requests whose buffers overlap, queued together behind a large request
+    where the scheduler would batch them: a chained pair (B reads A's output),
+    a shared output (D writes C's output), a write over an earlier request's
+    input (F writes E's input) and two outputs that overlap in part (H's rows
+    start halfway down G's).  Each runs as if alone, in submission order; no
+    launch fails; the unrelated requests in the mix equal their lone calls
+    bitwise."""
+    import torch
+
+    def lone(a, k):
+        o = torch.empty_strided(a.size(), a.stride(), dtype=a.dtype, device="cuda")
+        cs.conv_sep5_1pass(a, o, k)
+        return o
+
+    ks = [synth.taps_random(9300 + i) for i in range(16)]
+    R, C = 96, 200
+    x = torch.rand(3, R, C, device="cuda")
+    y = gu.nan_like(x)                                  # A: x -> y
+    z = gu.nan_like(x)                                  # B: y -> z
+    p, r = torch.rand(3, R, C, device="cuda"), torch.rand(3, R, C, device="cuda")
+    q = gu.nan_like(x)                                  # C: p -> q, then D: r -> q
+    s, u = torch.rand(3, R, C, device="cuda"), torch.rand(3, R, C, device="cuda")
+    s0 = s.clone()
+    t = gu.nan_like(x)                                  # E: s -> t, then F: u -> s
+    src_g = torch.rand(3, 3 * R // 2, C, device="cuda")
+    src_h = torch.rand(3, 3 * R // 2, C, device="cuda")
+    big = torch.full((3, 3 * R // 2, C), float("nan"), device="cuda")
+    g_in, g_out = src_g[:, :R], big[:, :R]              # G
+    h_in, h_out = src_h[:, :R], big[:, R // 2:R // 2 + R]  # H: overlaps G's rows R/2..R-1
+    others = _requests(12, seed=31)
+    other_outs = [gu.nan_like(a) for a, _ in others]
+
+    exp_y = lone(x, ks[0])
+    exp_z = lone(exp_y, ks[1])
+    exp_q = lone(r, ks[3])
+    exp_t = lone(s0, ks[4])
+    exp_s = lone(u, ks[5])
+    exp_g, exp_h = lone(g_in, ks[6]), lone(h_in, ks[7])
+    exp_others = [lone(a, k) for a, k in others]
+    blocker = torch.rand(3, 4096, 8192, device="cuda")
+    blocker_out = torch.empty_like(blocker)
+    torch.cuda.synchronize()
+
+    srv = cs.conv_serve_create(1 << 33, max_slots=32, n_streams=2, max_batch=8,
+                               queue_only=queue_only)
+    try:
+        tickets = [srv.submit(blocker, blocker_out, ks[15])]
+        order = [(x, y, ks[0]), (y, z, ks[1]), (p, q, ks[2]), (r, q, ks[3]),
+                 (s, t, ks[4]), (u, s, ks[5]), (g_in, g_out, ks[6]), (h_in, h_out, ks[7])]
+        for i, (a, o, k) in enumerate(order):
+            tickets.append(srv.submit(a, o, k))
+            a2, k2 = others[i]
+            tickets.append(srv.submit(a2, other_outs[i], k2))
+        for i in range(len(order), len(others)):
+            tickets.append(srv.submit(others[i][0], other_outs[i], others[i][1]))
+        _wait_all(srv, tickets)
+        st = srv.stats()
+    finally:
+        srv.destroy()
+    assert st["failed"] == 0 and st["completed"] == len(tickets)
+    assert torch.equal(y, exp_y) and torch.equal(z, exp_z)
+    assert torch.equal(q, exp_q)
+    assert torch.equal(t, exp_t) and torch.equal(s, exp_s)
+    assert torch.equal(big[:, :R // 2], exp_g[:, :R // 2])
+    assert torch.equal(big[:, R // 2:R // 2 + R], exp_h)
+    for o, e in zip(other_outs, exp_others):
+        assert torch.equal(o, e)
+    print("serve stats (overlapping requests)", st)
