@@ -338,7 +338,10 @@ typedef struct {
 } conv_tile_cfg;
 
 /*
- * kind: 0 = single-image kernels (1pass/2pass), 1 = batch kernel.
+ * kind: 0 = single-image kernels (fused 1pass, 2pass, image copy), 1 = batch
+ * kernel, 2 = single-image direct 25-tap kernel (CONV_1PASS_DIRECT25, which
+ * is bound by its vector ALU work rather than by memory; its 16-bit defaults
+ * are 16-row bands).
  * get/set address the default configuration of (dtype, kind).  set also
  * drops what the tuner installed for (dtype, kind), so an explicit
  * configuration applies to every workload size.
@@ -362,7 +365,8 @@ conv_status conv_get_tile_cfg_for(int32_t dtype, int32_t kind, uint64_t footprin
  * workload with HIP events (`reps` timed launches each, after one warm-up),
  * installs the fastest for the workload's storage type, kind and size class
  * and returns it in *best, with its median time per launch in *best_ms.
- * kind 0 tunes on image 0 alone (fused 1pass), kind 1 on the whole batch.
+ * kind 0 tunes on image 0 alone (fused 1pass), kind 2 on image 0 alone
+ * (direct 25-tap 1pass), kind 1 on the whole batch.
  * Synchronises `stream`.  Calls of other size classes keep their own choice.
  * The launches reuse the same buffers, so a workload whose input and output
  * fit the GPU's 256 MB last-level cache is timed with a warm cache (where

@@ -26,7 +26,7 @@ CONV_F32, CONV_F16, CONV_BF16 = 0, 1, 2
 CONV_1PASS_FUSED, CONV_1PASS_DIRECT25 = 0, 1
 # bytes of the static device workspace of conv_sep5_2pass_noalloc (per GPU)
 CONV_NOALLOC_SCRATCH_BYTES = 128 << 20
-KIND_IMAGE, KIND_BATCH = 0, 1
+KIND_IMAGE, KIND_BATCH, KIND_DIRECT = 0, 1, 2
 
 _STATUS_NAMES = {0: "CONV_OK", -1: "CONV_EINVAL", -2: "CONV_EALIAS", -3: "CONV_ENOMEM",
                  -4: "CONV_EHIP", -5: "CONV_EAGAIN", -6: "CONV_ENOTFOUND"}

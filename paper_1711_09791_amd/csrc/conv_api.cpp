@@ -118,17 +118,20 @@ static std::mutex g_cfg_mu;
 // Defaults from tile sweeps on MI355X (3 x 4096 x 4096 single image; the
 // 64-image uneven batch): 8-row bands, one wave per workgroup, XCDs taking
 // turns on chunks of 8 band rows (batch: of 64 tiles), and for batches one
-// workgroup per tile; conv_tune re-derives them for a given workload.
-static conv_tile_cfg g_cfg[3][2] = {
-    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
-    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
-    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
+// workgroup per tile.  The 16-bit direct 25-tap kernel, bound by its vector
+// ALU work, runs 16-row bands (the walking band form, which keeps five
+// decoded rows live): 50.0 / 48.2 us against 52.1 / 53.1 us with 8-row bands
+// for FP16 / BF16.  conv_tune re-derives them for a given workload.
+static conv_tile_cfg g_cfg[3][kKinds] = {
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}, {16, 1, 0, 8, 0}},
+    {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}, {16, 1, 0, 8, 0}},
 };
 
 // Configurations the tuner installed, per storage type, kind and workload
 // size class (conv_tune, conv_tune_load); they take precedence over the
 // defaults above for workloads of their class.
-static TunedEntry g_tuned[3][2][kSizeClasses];
+static TunedEntry g_tuned[3][kKinds][kSizeClasses];
 
 conv_tile_cfg get_cfg(int dtype, int kind) {
     std::lock_guard<std::mutex> g(g_cfg_mu);
@@ -155,19 +158,19 @@ TunedEntry get_tuned(int dtype, int kind, int cls) {
 void put_tuned(int dtype, int kind, int cls, const TunedEntry &e) {
     std::lock_guard<std::mutex> g(g_cfg_mu);
     g_tuned[dtype][kind][cls] = e;
-    if (kind == 0) g_tuned[dtype][0][cls].cfg.persist_wgs_per_cu = 0;
+    if (kind != kKindBatch) g_tuned[dtype][kind][cls].cfg.persist_wgs_per_cu = 0;
 }
 
 void put_default_cfg(int dtype, int kind, const conv_tile_cfg &c) {
     std::lock_guard<std::mutex> g(g_cfg_mu);
     g_cfg[dtype][kind] = c;
-    if (kind == 0) g_cfg[dtype][0].persist_wgs_per_cu = 0;
+    if (kind != kKindBatch) g_cfg[dtype][kind].persist_wgs_per_cu = 0;
 }
 
 bool cfg_ok(const conv_tile_cfg *c, int kind) {
     if (c->rows_per_tile < 1 || c->rows_per_tile > 4096) return false;
     if (c->waves_per_wg != 1 && c->waves_per_wg != 2 && c->waves_per_wg != 4) return false;
-    if (kind == 1 && (c->persist_wgs_per_cu < 0 || c->persist_wgs_per_cu > 32)) return false;
+    if (kind == kKindBatch && (c->persist_wgs_per_cu < 0 || c->persist_wgs_per_cu > 32)) return false;
     if (c->xcd_slabs < 0 || c->xcd_slabs > 4096) return false;
     if (c->pack_tail < -1 || c->pack_tail > 1) return false;
     return true;
@@ -545,7 +548,8 @@ conv_status conv_sep5_1pass(const void *d_in, void *d_out, const float k[5],
     const bool copy_back = d_in == (const void *)d_out;
     if (!copy_back && overlaps(d_in, L.extent_bytes, d_out, L.extent_bytes))
         return set_error(CONV_EALIAS, "input and output partially overlap");
-    const conv_tile_cfg cfg = get_cfg_for(img->dtype, 0, 2 * (uint64_t)L.extent_bytes);
+    const conv_tile_cfg cfg = get_cfg_for(img->dtype, mode == CONV_1PASS_FUSED ? kKindImage : kKindDirect,
+                                          2 * (uint64_t)L.extent_bytes);
     const int kmode = mode == CONV_1PASS_FUSED ? MODE_FUSED : MODE_DIRECT25;
     ImgDev d;
     if (!copy_back) {
@@ -743,7 +747,7 @@ conv_status conv_sep5_batch(int32_t n, const void *const *d_in, void *const *d_o
 
 conv_status conv_get_tile_cfg(int32_t dtype, int32_t kind, conv_tile_cfg *cfg) {
     clear_error();
-    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind >= kKinds || !cfg)
         return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
     *cfg = get_cfg(dtype, kind);
     return CONV_OK;
@@ -751,7 +755,7 @@ conv_status conv_get_tile_cfg(int32_t dtype, int32_t kind, conv_tile_cfg *cfg) {
 
 conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *cfg) {
     clear_error();
-    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind >= kKinds || !cfg)
         return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
     if (!cfg_ok(cfg, kind)) return set_error(CONV_EINVAL, "tile configuration out of range");
     put_default_cfg(dtype, kind, *cfg);
@@ -764,7 +768,7 @@ conv_status conv_set_tile_cfg(int32_t dtype, int32_t kind, const conv_tile_cfg *
 conv_status conv_get_tile_cfg_for(int32_t dtype, int32_t kind, uint64_t footprint_bytes,
                                   conv_tile_cfg *cfg, int32_t *tuned) {
     clear_error();
-    if (dtype < 0 || dtype > 2 || kind < 0 || kind > 1 || !cfg)
+    if (dtype < 0 || dtype > 2 || kind < 0 || kind >= kKinds || !cfg)
         return set_error(CONV_EINVAL, "bad dtype/kind/cfg");
     load_tune_cache_once();
     const TunedEntry t = get_tuned(dtype, kind, size_class(footprint_bytes));

@@ -24,6 +24,13 @@ struct Layout {
     bool hwc = false;            // planes interleaved per pixel (plane_stride == 1)
 };
 
+// Tile configuration kinds: 0 the single-image kernels (fused single pass,
+// two-pass, copy), 1 the batch kernel, 2 the single-image direct 25-tap
+// kernel (VALU-bound where the others are memory-bound, so it takes its own
+// tiles).
+constexpr int kKinds = 3;
+constexpr int kKindImage = 0, kKindBatch = 1, kKindDirect = 2;
+
 conv_status set_error(conv_status st, const char *fmt, ...);
 void clear_error();
 conv_status hip_error(hipError_t e, const char *what);

@@ -39,7 +39,7 @@ std::vector<conv_tile_cfg> candidates(int kind) {
     std::vector<conv_tile_cfg> c;
     const int ths[] = {4, 8, 16, 32, 64};
     const int waves[] = {1, 2, 4};
-    if (kind == 0) {
+    if (kind != kKindBatch) {
         const int xcd[] = {0, 1, 4, 8, 16};
         for (int x : xcd)
             for (int th : ths)
@@ -109,7 +109,7 @@ conv_status parse(const std::string &text, std::vector<FileEntry> *out) {
         FileEntry f{};
         double ms = 0.0;
         conv_tile_cfg &c = f.e.cfg;
-        const bool ok = int_of(b, e, "dtype", 0, 2, &f.dtype) && int_of(b, e, "kind", 0, 1, &f.kind) &&
+        const bool ok = int_of(b, e, "dtype", 0, 2, &f.dtype) && int_of(b, e, "kind", 0, kKinds - 1, &f.kind) &&
                         int_of(b, e, "size_class", 0, kSizeClasses - 1, &f.cls) &&
                         int_of(b, e, "rows_per_tile", 1, 4096, &c.rows_per_tile) &&
                         int_of(b, e, "waves_per_wg", 1, 4, &c.waves_per_wg) &&
@@ -149,7 +149,7 @@ conv_status save_file(const char *path) {
     std::fprintf(fp, "{\"format\": \"%s\", \"arch\": \"gfx950\", \"entries\": [", kFormat);
     bool first = true;
     for (int d = 0; d < 3; ++d)
-        for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < kKinds; ++k)
             for (int c = 0; c < kSizeClasses; ++c) {
                 const TunedEntry t = get_tuned(d, k, c);
                 if (!t.valid) continue;
@@ -198,14 +198,15 @@ extern "C" conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_i
                                  int32_t reps, hipStream_t stream, conv_tile_cfg *best,
                                  float *best_ms) {
     clear_error();
-    if (kind != 0 && kind != 1) return set_error(CONV_EINVAL, "kind %d is not 0 or 1", kind);
+    if (kind < 0 || kind >= kKinds) return set_error(CONV_EINVAL, "kind %d is not 0, 1 or 2", kind);
     if (n < 1 || !d_in || !d_out || !k || !imgs || !best || reps < 1 || reps > 10000)
         return set_error(CONV_EINVAL, "bad tuner arguments");
     const int dtype = imgs[0].dtype;
     if (dtype < 0 || dtype > 2) return set_error(CONV_EINVAL, "bad dtype %d", dtype);
     load_tune_cache_once();
-    // the workload's size class: image 0 alone for kind 0, the whole batch for kind 1
-    const int cls = size_class(batch_footprint(kind == 0 ? 1 : n, imgs));
+    // the workload's size class: image 0 alone for kinds 0 and 2, the whole
+    // batch for kind 1
+    const int cls = size_class(batch_footprint(kind == kKindBatch ? n : 1, imgs));
     const conv_tile_cfg orig = get_cfg(dtype, kind);
     const TunedEntry orig_tuned = get_tuned(dtype, kind, cls);
     // candidates run as the default with this class's tuned entry set aside
@@ -217,7 +218,10 @@ extern "C" conv_status conv_tune(int32_t kind, int32_t n, const void *const *d_i
         if (rc == CONV_OK && hipEventCreate(&e) != hipSuccess)
             rc = set_error(CONV_EHIP, "hipEventCreate failed");
     auto run_once = [&]() -> conv_status {
-        if (kind == 0) return conv_sep5_1pass(d_in[0], d_out[0], k, &imgs[0], CONV_1PASS_FUSED, stream);
+        if (kind == kKindImage)
+            return conv_sep5_1pass(d_in[0], d_out[0], k, &imgs[0], CONV_1PASS_FUSED, stream);
+        if (kind == kKindDirect)
+            return conv_sep5_1pass(d_in[0], d_out[0], k, &imgs[0], CONV_1PASS_DIRECT25, stream);
         return conv_sep5_batch(n, d_in, d_out, k, imgs, CONV_1PASS_FUSED, stream);
     };
     float best_t = 1e30f;

@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads, exports every symbol the
 header declares, and rejects bad arguments before any HIP call."""
 import ctypes
+import json
 import os
 import re
 
@@ -495,3 +496,53 @@ def test_noalloc_rejects_what_does_not_fit_before_any_hip_call():
     # nothing to do: no HIP call, no error
     empty = conv_image(3, 0, 4096, cs.CONV_F32, 0, 0)
     assert L.conv_sep5_2pass_noalloc(None, None, kk, ctypes.byref(empty), cs.CONV_F32, None) == cs.CONV_OK
+
+
+def test_direct_kind_has_its_own_configuration():
+    """Kind 2 (the direct 25-tap single-image kernel) is configured apart from
+    kind 0: 16-row bands by default for 16-bit storage, 8 for FP32; setting
+    one kind leaves the other alone; kind 3 does not exist."""
+    assert cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT).rows_per_tile == 16
+    assert cs.conv_get_tile_cfg(cs.CONV_BF16, cs.KIND_DIRECT).rows_per_tile == 16
+    assert cs.conv_get_tile_cfg(cs.CONV_F32, cs.KIND_DIRECT).rows_per_tile == 8
+    d = cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT)
+    i = cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_IMAGE)
+    try:
+        cs.conv_set_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT, 32, 2, 0, 4)
+        assert cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT).rows_per_tile == 32
+        assert cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_IMAGE).as_dict() == i.as_dict()
+        # a persistent grid applies to the batch kernel only
+        cs.conv_set_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT, 16, 1, 8, 8)
+        assert cs.conv_get_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT).persist_wgs_per_cu == 0
+    finally:
+        cs.conv_set_tile_cfg(cs.CONV_F16, cs.KIND_DIRECT, **d.as_dict())
+    with pytest.raises(cs.ConvError):
+        cs.conv_get_tile_cfg(0, 3)
+    with pytest.raises(cs.ConvError):
+        cs.conv_set_tile_cfg(0, 3, 8, 1)
+
+
+def test_tune_cache_holds_direct_kind(tmp_path):
+    d = cs.conv_get_tile_cfg(cs.CONV_BF16, cs.KIND_DIRECT).as_dict()
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"format": "convsep5-tune-1", "entries": [
+        {"dtype": 2, "kind": 2, "size_class": 1, "rows_per_tile": 32, "waves_per_wg": 1,
+         "persist_wgs_per_cu": 0, "xcd_slabs": 8, "pack_tail": 0, "ms": 0.05}]}))
+    try:
+        cs.conv_tune_load(str(p))
+        c, tuned = cs.conv_get_tile_cfg_for(cs.CONV_BF16, cs.KIND_DIRECT, 200 << 20)
+        assert tuned and c.rows_per_tile == 32
+        assert not cs.conv_get_tile_cfg_for(cs.CONV_BF16, cs.KIND_IMAGE, 200 << 20)[1]
+        q = tmp_path / "saved.json"
+        cs.conv_tune_save(str(q))
+        assert any(e["kind"] == 2 and e["rows_per_tile"] == 32
+                   for e in json.loads(q.read_text())["entries"])
+    finally:
+        cs.conv_set_tile_cfg(cs.CONV_BF16, cs.KIND_DIRECT, **d)
+    assert not cs.conv_get_tile_cfg_for(cs.CONV_BF16, cs.KIND_DIRECT, 200 << 20)[1]
+    bad = tmp_path / "bad.json"
+    bad.write_text(json.dumps({"format": "convsep5-tune-1", "entries": [
+        {"dtype": 2, "kind": 3, "size_class": 1, "rows_per_tile": 32, "waves_per_wg": 1,
+         "persist_wgs_per_cu": 0, "xcd_slabs": 8, "pack_tail": 0, "ms": 0.05}]}))
+    with pytest.raises(cs.ConvError):
+        cs.conv_tune_load(str(bad))

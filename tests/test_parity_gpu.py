@@ -70,22 +70,27 @@ def test_tiny_images_are_zero(shape):
 
 
 def test_every_tile_shape_is_bitwise_identical():
+    """Kind 0 (fused, two-pass) and kind 2 (direct 25-tap) configurations."""
     host = synth.image(41, 3, 150, 700)
     k = synth.taps_random(42)
     a = gu.to_device(host)
-    orig = cs.conv_get_tile_cfg(0, 0)
+    orig = cs.conv_get_tile_cfg(0, cs.KIND_IMAGE)
+    orig_d = cs.conv_get_tile_cfg(0, cs.KIND_DIRECT)
     try:
         base = {f: gu.to_host_bits(gu.run(f, a, k)) for f in FORMS}
         for th in (1, 3, 4, 8, 16, 17, 64, 200):
             for w in (1, 2, 4):
                 for x in (0, 1, 2, 8, 64):
-                    cs.conv_set_tile_cfg(0, 0, th, w, 0, x)
+                    cs.conv_set_tile_cfg(0, cs.KIND_IMAGE, th, w, 0, x)
+                    cs.conv_set_tile_cfg(0, cs.KIND_DIRECT, th, w, 0, x)
                     for f in FORMS:
                         got = gu.to_host_bits(gu.run(f, a, k))
                         assert np.array_equal(got, base[f]), (th, w, x, f)
     finally:
-        cs.conv_set_tile_cfg(0, 0, orig.rows_per_tile, orig.waves_per_wg, 0, orig.xcd_slabs)
+        cs.conv_set_tile_cfg(0, cs.KIND_IMAGE, **orig.as_dict())
+        cs.conv_set_tile_cfg(0, cs.KIND_DIRECT, **orig_d.as_dict())
     gu.check_f32(base["fused"], gu.oracle_of(host, k))
+    gu.check_f32(base["direct"], gu.oracle_of(host, k))
 
 
 def test_pitched_and_offset_layouts():

@@ -102,3 +102,35 @@ def test_16bit_full_size_sampled(dtype):
         e, n_mid = gate(got, ref, dtype)
         print(f"{dtype} {f} 3x4096x4096 sampled: max rel err {e:.3e}, {n_mid} midpoint cases")
         assert e <= LIMIT[dtype] * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_16bit_direct_every_tile_shape_and_tuner(dtype):
+    """The direct 25-tap kernel's own configurations (kind 2: fixed 4- and
+    8-row bands, walking bands of 16 and more, several waves per workgroup)
+    give bitwise identical 16-bit results that pass the storage gate, and
+    the tuner runs on kind 2 and installs its choice for the workload."""
+    import paper_1711_09791_amd as cs
+
+    code = {"f16": cs.CONV_F16, "bf16": cs.CONV_BF16}[dtype]
+    host32 = synth.image(21, 3, 170, 1100)
+    bits = synth.to_storage(host32, dtype)
+    k = synth.taps_random(22)
+    a = gu.to_device(bits, dtype)
+    ref = gu.oracle_of(bits, k, dtype)
+    orig = cs.conv_get_tile_cfg(code, cs.KIND_DIRECT)
+    try:
+        base = gu.to_host_bits(gu.run("direct", a, k))
+        gate(base, ref, dtype)
+        for th in (1, 4, 8, 16, 17, 32, 200):
+            for w in (1, 2, 4):
+                cs.conv_set_tile_cfg(code, cs.KIND_DIRECT, th, w, 0, 8)
+                got = gu.to_host_bits(gu.run("direct", a, k))
+                assert np.array_equal(got, base), (th, w)
+        o = gu.nan_like(a)
+        best, ms = cs.conv_tune(cs.KIND_DIRECT, [a], [o], [k], reps=2)
+        cfg, tuned = cs.conv_get_tile_cfg_for(code, cs.KIND_DIRECT, 2 * a.numel() * a.element_size())
+        assert tuned and cfg.as_dict() == best.as_dict() and ms > 0
+        assert np.array_equal(gu.to_host_bits(gu.run("direct", a, k)), base)
+    finally:
+        cs.conv_set_tile_cfg(code, cs.KIND_DIRECT, **orig.as_dict())
