@@ -220,16 +220,22 @@ int64_t fill_desc(ImgDev *d, const void *in, void *out, float *tmp, const conv_i
     d->xcd_slabs = cfg.xcd_slabs;
     fill_taps(&d->tp, k);
     if (L.empty) return 0;
-    // A narrow last strip (at most a half or a quarter of 64*v columns) of an
-    // aligned image is packed: one wave takes it for 2 or 4 bands.  Its rows
-    // then share one buffer resource, whose span must stay below the
-    // out-of-range offset.
+    // The last strip of an aligned image, when narrower than a wave, is packed:
+    // cut into a piece of 32 lanes (one wave for 2 bands) and pieces of 16
+    // lanes (one wave for 4 bands), so that at most 15 lanes of the last piece
+    // stay idle.  The rows of a packed tile share one buffer resource, whose
+    // span must stay below the out-of-range offset.
     if (pack && al && cfg.waves_per_wg == 1 && (d->th == 4 || d->th == 8) && d->nb >= 2) {
-        const int r = img->cols - (d->ns - 1) * sw;
-        const int q = r <= 16 * v ? 4 : (r <= 32 * v ? 2 : 1);
-        if (q > 1 && (int64_t)(q * d->th + 4) * L.pitch * L.esz < ((int64_t)1 << 31) - 64) {
-            d->tq = q;
-            return (int64_t)img->planes * ((int64_t)d->nb * (d->ns - 1) + (d->nb + q - 1) / q);
+        const int lanes = (img->cols - (d->ns - 1) * sw) / v;  // cols % v == 0 here
+        const int p32 = lanes > 16 && lanes < 64 ? 1 : 0;
+        const int p16 = lanes <= 16 ? 1 : (lanes <= 32 ? 0 : (lanes <= 48 ? 1 : (lanes < 64 ? 2 : 0)));
+        const int G = p16 ? 4 : 2;
+        if ((p32 || p16) && (int64_t)(G * d->th + 4) * L.pitch * L.esz < ((int64_t)1 << 31) - 64) {
+            d->tq = G;
+            d->pk32 = (int16_t)p32;
+            d->pk16 = (int16_t)p16;
+            const int64_t nb = d->nb, m = d->ns - 1;
+            return (int64_t)img->planes * (nb * m + p32 * ((nb + 1) / 2) + p16 * ((nb + G - 1) / G));
         }
     }
     return (int64_t)img->planes * d->nsg * d->nb;

@@ -46,10 +46,14 @@ struct ImgDev {
     int32_t xcd_slabs;    // 1: each XCD takes one contiguous slab of tiles;
                           // c >= 2: XCDs take turns on chunks of c band rows
     int32_t keep_out;     // 1: output stores stay cached (copy-back scratch read next)
-    int32_t tq;           // fused/direct with one wave per workgroup: > 1 packs the
-                          // last (narrow) strip of tq consecutive bands into one
-                          // wave, 64/tq lanes per band; 0 or 1: no packing
-    int32_t reserved;
+    int32_t tq;           // fused/direct with one wave per workgroup, aligned images:
+                          // > 1 packs the last (narrow) strip, cut into pieces of
+                          // 32 and 16 lanes' width: a 32-lane piece serves 2 bands
+                          // per wave, a 16-lane piece 4; the bands go in groups of
+                          // tq (4 when there is a 16-lane piece, else 2);
+                          // 0 or 1: no packing
+    int16_t pk32;         // packed pieces, left to right: 32-lane pieces (0 or 1)
+    int16_t pk16;         //   then 16-lane pieces (0 .. 2)
     int64_t tile_begin;   // batch: this image's first tile in the launch
     int64_t tile_end;     // batch: one past its last tile
     Taps tp;

@@ -697,16 +697,18 @@ __device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, i
 }
 
 // ---- packed last strip (fused and direct25) ------------------------------------------
-// A last strip of r <= 64*VEC/Q columns would leave most lanes of its wave
-// idle, and a wave costs about the same time whether its lanes are busy or
-// not.  Here one wave takes that strip for Q consecutive bands (Q = 2 or 4):
-// lane group g (S = 64/Q lanes) works on band band0 + g.  The groups read
-// different rows, so the buffer resource spans the rows of all Q bands and
-// each lane adds its own row offset; the range check then no longer stops
-// lanes past the right edge, so their stores get an out-of-range offset
-// explicitly (their loads may read the next row, which only reaches outputs
-// in the zero frame).  The first and last lane of each group fetch the group's
-// halo columns.
+// A last strip narrower than a wave's 64*VEC columns would leave lanes of its
+// wave idle, and a wave costs about the same time whether its lanes are busy
+// or not.  The last strip is therefore cut into pieces, left to right: at most
+// one of 32 lanes' width and up to two of 16 (the last piece may be partly
+// past the right edge).  One wave takes a piece for Q consecutive bands (Q = 2
+// for a 32-lane piece, 4 for a 16-lane one): lane group g (64/Q lanes) works
+// on band band0 + g.  The groups read different rows, so the buffer resource
+// spans the rows of all Q bands and each lane adds its own row offset; the
+// range check then no longer stops lanes past the right edge, so their stores
+// get an out-of-range offset explicitly (their loads may read the next row,
+// which only reaches outputs in the zero frame).  The first and last lane of
+// each group fetch the group's halo columns.
 //
 // Horizontal neighbours inside a group, with no per-lane select (a select on
 // the lane's position lets the compiler put the move under a lane mask, and a
@@ -717,20 +719,32 @@ __device__ __forceinline__ void band_copy(const ImgDev &im, int plane, int xs, i
 //          lane 15's and 47's value from a wave_shr:1 move written only to
 //          rows 1 and 3, bank 0 (lanes 16..19, 48..51; on 17..19 and 49..51
 //          it writes the value they already hold);
-//   right: wave_shl:1 as in the full strips.  The last lane of a group then
-//          holds the next group's first columns, but they only reach its
-//          outputs at columns >= W-2 (the group covers the strip's last
-//          column), which are written as zero.
+//   right: the mirror image: row_shl:1 within each row, so a row's lane 15
+//          keeps its own right halo; with 2 groups, lanes 15 and 47 (row 0
+//          and 2, lane 15) then take lane 16's and 48's value from a
+//          wave_shl:1 move written only to rows 0 and 2, bank 3 (lanes
+//          12..15, 44..47).  A piece that is not the last one thus gets its
+//          right neighbours from its own halo load, not from the next group.
 __device__ __forceinline__ uint32_t left_in_row(uint32_t src, uint32_t old) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x111, 0xf, 0xf, false);
 }
 __device__ __forceinline__ uint32_t left_rows13_bank0(uint32_t src, uint32_t old) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xa, 0x1, false);
 }
+__device__ __forceinline__ uint32_t right_in_row(uint32_t src, uint32_t old) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x101, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t right_rows02_bank3(uint32_t src, uint32_t old) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x130, 0x5, 0x8, false);
+}
 // q2: groups of 32 lanes (uniform across the wave)
 __device__ __forceinline__ uint32_t left_in_group(uint32_t src, uint32_t halo, bool q2) {
     const uint32_t a = left_in_row(src, halo);
     return q2 ? left_rows13_bank0(src, a) : a;
+}
+__device__ __forceinline__ uint32_t right_in_group(uint32_t src, uint32_t halo, bool q2) {
+    const uint32_t a = right_in_row(src, halo);
+    return q2 ? right_rows02_bank3(src, a) : a;
 }
 template <class D>
 __device__ __forceinline__ void decode_group(const Raw<D, true> &r, bool q2,
@@ -742,11 +756,11 @@ __device__ __forceinline__ void decode_group(const Raw<D, true> &r, bool q2,
         v[3] = __uint_as_float(r.m.y);
         v[4] = __uint_as_float(r.m.z);
         v[5] = __uint_as_float(r.m.w);
-        v[6] = __uint_as_float(from_right(r.m.x, r.h0));
-        v[7] = __uint_as_float(from_right(r.m.y, r.h1));
+        v[6] = __uint_as_float(right_in_group(r.m.x, r.h0, q2));
+        v[7] = __uint_as_float(right_in_group(r.m.y, r.h1, q2));
     } else {
         const uint32_t l = left_in_group(r.m.w, r.h0, q2);
-        const uint32_t rr = from_right(r.m.x, r.h0);
+        const uint32_t rr = right_in_group(r.m.x, r.h0, q2);
         const uint32_t w[4] = {r.m.x, r.m.y, r.m.z, r.m.w};
         v[0] = dec(D{}, l);
         v[1] = dec(D{}, l >> 16);
@@ -829,16 +843,16 @@ __device__ __forceinline__ void store_group(__amdgpu_buffer_rsrc_t rs, uint32_t 
     }
 }
 
-// The packed strip starting at column xs for bands band0 .. band0+qg-1
-// (qg <= Q); every band has TH rows except possibly the image's last.
+// The packed piece starting at column xs (32 lanes wide if q2, else 16) for
+// bands band0 .. band0+qg-1 (qg <= Q); every band has TH rows except possibly
+// the image's last.
 template <class D, bool AL, int MODE, int TH, int SAUX>
 __device__ __forceinline__ void band_packed(const ImgDev &im, int plane, int xs, int band0, int qg,
-                                            int lane) {
+                                            bool q2, int lane) {
     constexpr int VEC = D::VEC;
     constexpr bool DIRECT = MODE == MODE_DIRECT25;
     constexpr int WN = DIRECT ? VEC + 4 : VEC;
     const int H = im.rows, W = im.cols;
-    const bool q2 = im.tq == 2;
     const int lgs = q2 ? 5 : 4;                    // log2 of the lanes per group
     const int grp = lane >> lgs, ln = lane & ((1 << lgs) - 1);
     const bool first = ln == 0, last = ln == (1 << lgs) - 1;
@@ -925,24 +939,44 @@ template <class D, bool AL, int MODE, int TH, int SAUX>
 __device__ __forceinline__ void run_strip_band(const ImgDev &im, int plane, int strip, int band,
                                                int lane);
 
-// Tiles of an image whose last strip is packed (im.tq = Q > 1): per plane, the
-// bands go in groups of Q; a group's tiles are the m = ns-1 full strips of
-// each of its bands (band-major, strip fastest), then one packed tile for the
-// last strip of all its bands.
+// Tiles per group of tq bands of an image whose last strip is packed: the
+// m = ns-1 full strips of each band, one tile per 2 bands for the 32-lane
+// piece, one per group for each 16-lane piece.
+__device__ __forceinline__ int64_t packed_group_tiles(const ImgDev &im) {
+    return (int64_t)im.tq * (im.ns - 1) + im.pk32 * (im.tq / 2) + im.pk16;
+}
+
+// Tiles of an image whose last strip is packed (im.tq = G > 1): per plane, the
+// bands go in groups of G; a group's tiles are the m = ns-1 full strips of
+// each of its bands (band-major, strip fastest), then the tiles of the
+// pieces of the last strip, left to right (for a 32-lane piece one per 2
+// bands of the group, for a 16-lane piece one for the whole group).
 template <class D, bool AL, int MODE, int TH, int SAUX>
 __device__ __forceinline__ void run_tile_packed(const ImgDev &im, int64_t lt, int lane) {
-    const int Q = im.tq, m = im.ns - 1;
-    const int64_t G = (int64_t)Q * m + 1;
-    const int64_t TP = (int64_t)im.nb * m + (im.nb + Q - 1) / Q;
+    const int G = im.tq, m = im.ns - 1;
+    const int64_t per = packed_group_tiles(im);
+    const int64_t TP = (int64_t)im.nb * m + (int64_t)im.pk32 * ((im.nb + 1) / 2) +
+                       (int64_t)im.pk16 * ((im.nb + G - 1) / G);
     const int plane = (int)(lt / TP);
     const int64_t r = lt % TP;
-    const int g = (int)(r / G);
-    const int rr = (int)(r % G);
-    const int qg = min(Q, im.nb - g * Q);
-    if (rr < qg * m)
-        run_strip_band<D, AL, MODE, TH, SAUX>(im, plane, rr % m, g * Q + rr / m, lane);
-    else
-        band_packed<D, AL, MODE, TH, SAUX>(im, plane, m * (WAVE * D::VEC), g * Q, qg, lane);
+    const int g = (int)(r / per);
+    int rr = (int)(r % per);
+    const int qg = min(G, im.nb - g * G);
+    if (rr < qg * m) {
+        run_strip_band<D, AL, MODE, TH, SAUX>(im, plane, rr % m, g * G + rr / m, lane);
+        return;
+    }
+    rr -= qg * m;
+    const int xs = m * (WAVE * D::VEC);
+    const int t32 = im.pk32 ? (qg + 1) / 2 : 0;
+    if (rr < t32) {
+        band_packed<D, AL, MODE, TH, SAUX>(im, plane, xs, g * G + 2 * rr, min(2, qg - 2 * rr), true,
+                                           lane);
+        return;
+    }
+    rr -= t32;
+    band_packed<D, AL, MODE, TH, SAUX>(im, plane, xs + (im.pk32 * 32 + rr * 16) * D::VEC, g * G, qg,
+                                       false, lane);
 }
 
 // Kernels that take packed last strips: fused, and direct25 for FP32 (the
@@ -1017,8 +1051,7 @@ __device__ __forceinline__ int xcd_chunk_remap(int b, int n, int64_t T) {
 // xcd_slabs / tq band groups, at least one).
 template <bool PK>
 __device__ __forceinline__ int64_t chunk_tiles(const ImgDev &im) {
-    if (PK && im.tq > 1)
-        return (int64_t)max(1, im.xcd_slabs / im.tq) * ((int64_t)im.tq * (im.ns - 1) + 1);
+    if (PK && im.tq > 1) return (int64_t)max(1, im.xcd_slabs / im.tq) * packed_group_tiles(im);
     return (int64_t)im.xcd_slabs * im.nsg;
 }
 

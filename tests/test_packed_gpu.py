@@ -1,9 +1,12 @@
-"""Packed last strips: an aligned image whose last column strip is at most a
-half (quarter) of 64*VEC columns wide has that strip taken by one wave for 2
-(4) consecutive bands.  Packing is forced on (pack_tail = 1) at these small
-sizes; each case is checked against the FP64 oracle and bitwise against the
-same launch with packing off (and the fused form against the two-pass form),
-with the pitch padding of the output left untouched."""
+"""Packed last strips: an aligned image whose last column strip is narrower
+than a wave (64*VEC columns) has that strip cut into a piece of 32 lanes,
+taken by one wave for 2 consecutive bands, and pieces of 16 lanes, taken by
+one wave for 4 bands (a strip of at most 16 lanes: one 16-lane piece; 17..32:
+one 32-lane piece; 33..48: 32 + 16; 49..63: 32 + 16 + 16).  Packing is forced
+on (pack_tail = 1) at these small sizes; each case is checked against the
+FP64 oracle and bitwise against the same launch with packing off (and the
+fused form against the two-pass form), with the pitch padding of the output
+left untouched."""
 import numpy as np
 import pytest
 
@@ -25,7 +28,7 @@ def _torch():
 
 @pytest.fixture
 def restore_cfg():
-    saved = {(d, kd): cs.conv_get_tile_cfg(d, kd).as_dict() for d in range(3) for kd in (0, 1)}
+    saved = {(d, kd): cs.conv_get_tile_cfg(d, kd).as_dict() for d in range(3) for kd in (0, 1, 2)}
     yield
     for (d, kd), c in saved.items():
         cs.conv_set_tile_cfg(d, kd, c["rows_per_tile"], c["waves_per_wg"],
@@ -33,11 +36,20 @@ def restore_cfg():
 
 
 def widths(dtype):
-    """Widths whose last strip packs 4, 2 or 1 bands, and single-strip images."""
+    """Widths whose last strip is cut into each set of pieces (16; 32; 32+16;
+    32+16+16 lanes) at both ends of their ranges, a full last strip, and
+    single-strip images."""
     v = VEC[dtype]
     sw = 64 * v
     return [16 * v, 16 * v - v, 32 * v, 17 * v, sw + v, sw + 16 * v, 2 * sw + 32 * v,
-            2 * sw + 33 * v, 5 * v, v]
+            2 * sw + 33 * v, 5 * v, v, 40 * v, sw + 48 * v, 49 * v, 2 * sw + 63 * v, sw + 56 * v,
+            2 * sw]
+
+
+def set_kind0_and_direct(dtype, th, pack, x=8):
+    """The same tile configuration for the fused (kind 0) and direct (kind 2) kernels."""
+    cs.conv_set_tile_cfg(DTYPE_CODE[dtype], cs.KIND_IMAGE, th, 1, 0, x, pack)
+    cs.conv_set_tile_cfg(DTYPE_CODE[dtype], cs.KIND_DIRECT, th, 1, 0, x, pack)
 
 
 def pitched(t, pad):
@@ -62,7 +74,7 @@ def check(dtype, got_bits, host_bits, k, margin=12):
 @pytest.mark.parametrize("th", [4, 8])
 def test_single_image_packed_strips(dtype, th, restore_cfg):
     torch = _torch()
-    cs.conv_set_tile_cfg(DTYPE_CODE[dtype], 0, th, 1, 0, 8, 1)
+    set_kind0_and_direct(dtype, th, 1)
     v = VEC[dtype]
     for i, C in enumerate(widths(dtype)):
         # heights: partial last band, partial last group of bands, one band
@@ -83,9 +95,9 @@ def test_single_image_packed_strips(dtype, th, restore_cfg):
             # direct25 (packed for FP32 only) vs the same launch unpacked
             buf_d, out_d = pitched(gu.nan_like(a), pad)
             cs.conv_sep5_1pass(ain, out_d, k, cs.CONV_1PASS_DIRECT25)
-            cs.conv_set_tile_cfg(DTYPE_CODE[dtype], 0, th, 1, 0, 8, -1)
+            set_kind0_and_direct(dtype, th, -1)
             ref_d = gu.run("direct", a, k)
-            cs.conv_set_tile_cfg(DTYPE_CODE[dtype], 0, th, 1, 0, 8, 1)
+            set_kind0_and_direct(dtype, th, 1)
             got_d = gu.to_host_bits(out_d.contiguous())
             check(dtype, got_d, host, k)
             assert np.array_equal(got_d, gu.to_host_bits(ref_d)), (dtype, th, P, R, C)
@@ -158,15 +170,27 @@ def test_packed_every_tile_order(restore_cfg):
     host = synth.image(5600, 3, 203, 4 * 64 * 4 + 36)       # FP32: last strip 36 columns
     a = gu.to_device(host)
     k = synth.taps_random(5601)
-    cs.conv_set_tile_cfg(0, 0, 8, 1, 0, 8, -1)
+    set_kind0_and_direct("f32", 8, -1)
     ref = gu.run("fused", a, k)
     ref_d = gu.run("direct", a, k)
     for x in (0, 1, 2, 3, 4, 16, 64):
         for th in (4, 8):
-            cs.conv_set_tile_cfg(0, 0, th, 1, 0, x, 1)
+            set_kind0_and_direct("f32", th, 1, x)
             assert torch.equal(gu.run("fused", a, k), ref), (x, th)
             assert torch.equal(gu.run("direct", a, k), ref_d), (x, th)
-    shapes = [(70, 256 + 20), (33, 512 + 100), (129, 60), (41, 1024 + 8)]
+    for C in (4 * 64 * 4 + 4 * 40, 3 * 64 * 4 + 4 * 60):   # last strip 40 and 60 lanes
+        host = synth.image(5602 + C, 3, 203, C)
+        b = gu.to_device(host)
+        set_kind0_and_direct("f32", 8, -1)
+        ref, ref_d = gu.run("fused", b, k), gu.run("direct", b, k)
+        for x in (0, 1, 2, 3, 4, 16, 64):
+            for th in (4, 8):
+                set_kind0_and_direct("f32", th, 1, x)
+                assert torch.equal(gu.run("fused", b, k), ref), (C, x, th)
+                assert torch.equal(gu.run("direct", b, k), ref_d), (C, x, th)
+        gu.check_f32(gu.to_host_bits(ref), gu.oracle_of(host, k))
+    shapes = [(70, 256 + 20), (33, 512 + 100), (129, 60), (41, 1024 + 8), (57, 512 + 160),
+              (90, 1024 + 232)]
     ins = [gu.to_device(synth.image(5610 + i, 3, h, w)) for i, (h, w) in enumerate(shapes)]
     ks = [synth.taps_random(5620 + i) for i in range(len(shapes))]
     cs.conv_set_tile_cfg(0, 1, 8, 1, 0, 8, -1)
