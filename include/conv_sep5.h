@@ -396,8 +396,8 @@ conv_status conv_tune_load(const char *path);
  * arrival order while a slot is free and their HBM footprint (input + output
  * bytes) fits the budget, packs the requests admitted together into one
  * launch on the next idle stream (the batch kernel; a lone request runs the
- * single-image kernel), and retires requests when the launch's event
- * completes.  Requests that arrive while others run are admitted into
+ * single-image kernel), and retires requests when the stream has written the
+ * launch's token into its completion word (pinned host memory).  Requests that arrive while others run are admitted into
  * the next launch, on another stream, so their work overlaps on the device.
  * Each result is bitwise identical to a lone conv_sep5_1pass (fused) call.
  * The queue is host memory (request descriptors); the images stay in device
@@ -425,10 +425,10 @@ typedef struct {
     int32_t queue_only;        /* 0: a submit that finds nothing queued and
                                   a stream idle launches its request itself
                                   (the scheduler retires it) while submits
-                                  are sparse (running mean gap >= 8 us,
-                                  about one launch's enqueue time); dense
-                                  arrivals go to the scheduler, which
-                                  batches them;
+                                  are sparse (the running mean gap and the
+                                  gap before this submit >= 8 us, about one
+                                  launch's enqueue time); dense arrivals go
+                                  to the scheduler, which batches them;
                                   1: every launch is made by the scheduler */
 } conv_serve_cfg;
 

@@ -18,8 +18,12 @@
 //      never share a launch;
 //   3. launch: each admitted group becomes ONE batch launch on its stream (a
 //      group of one the single-image kernel), after a wait on the producers'
-//      events, followed by a completion event;
-//   4. poll the in-flight events without pausing, or spin 2 ms and then
+//      events, followed by a stream write of the launch's token into that
+//      stream's completion word in pinned host memory;
+//   4. poll the completion words without pausing (plain loads of host
+//      memory, no HIP call, so the polling never contends with a launch in
+//      the HIP runtime; a launch not confirmed after 2 ms is checked with
+//      hipStreamQuery, which reports a failed stream), or spin 2 ms and then
 //      sleep when idle; while nothing was submitted or finished the loop
 //      skips the lock.
 // A submit that finds nothing queued and a stream idle launches its request
@@ -45,6 +49,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <memory>
@@ -68,13 +73,19 @@ enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3 };
 
 constexpr uint64_t kSpinIdleNs = 2000000;  // scheduler spins 2 ms after going idle
 // A submit launches its request itself only while the running mean gap
-// between submits is at least this long (about what a launch takes to
-// enqueue): then the submitting thread keeps up with its arrivals.
+// between submits, and the gap before this submit, are at least this long
+// (about what a launch takes to enqueue): then the submitting thread keeps up
+// with its arrivals.
 constexpr uint64_t kDirectGapNs = 8000;
 // The running mean: gap_mean += (gap - gap_mean) / 4, each gap clamped to
 // kGapClampNs so that a burst after an idle spell is seen within a few submits.
 constexpr uint64_t kGapClampNs = 100000;
 constexpr int kPoolBlock = 256;         // requests per pool block
+// A launch whose completion word has not shown its token this long after the
+// launch is checked with hipStreamQuery (a failed launch never writes it).
+constexpr uint64_t kStreamCheckNs = 2000000;
+// Completion words are one 64-byte line apart (in 8-byte words).
+constexpr int kDoneStride = 8;
 constexpr size_t kTicketTable0 = 1024;  // initial ticket table size (power of two)
 
 struct Req {
@@ -103,7 +114,8 @@ bool conflicts(const Req *a, const Req *b) {
 struct Launch {
     std::vector<Req *> reqs;
     uint64_t bytes = 0;
-    hipEvent_t ev = nullptr;
+    uint64_t token = 0;    // written to its stream's completion word after the kernel
+    uint64_t check_ns = 0; // next time to ask hipStreamQuery about it
     int stream = 0;
 };
 
@@ -127,7 +139,12 @@ struct conv_server {
     std::vector<Req *> free_reqs;
     std::vector<Req *> table;            // ticket & (size - 1) -> live request
     std::vector<hipEvent_t> ready_pool;  // producer-stream events
-    std::vector<hipEvent_t> event_pool;  // launch-completion events
+    // Completion words, one per stream (each stream runs one launch at a time),
+    // in pinned host memory: the stream writes a launch's token after its
+    // kernel; the scheduler reads them with plain loads.
+    uint64_t *done_host = nullptr;
+    uint64_t *done_dev = nullptr;
+    uint64_t next_token = 1;
     std::vector<char> stream_busy;
     std::vector<Launch> handoff;         // launched by a submitter, not yet polled
     uint64_t last_submit_ns = 0;
@@ -148,7 +165,7 @@ struct conv_server {
     std::vector<Launch> admit_locked();
     bool blocked_locked(const Req *r, const Launch &L) const;
     void retire_locked(Req *r, int state, uint64_t t_done);
-    conv_status enqueue(Launch &L, hipEvent_t done_ev);
+    conv_status enqueue(Launch &L);
     bool launched_locked(Launch &L, conv_status rc, uint64_t t_launch);
     Req *new_req_locked();
     void put_ticket_locked(Req *r);
@@ -269,15 +286,7 @@ std::vector<Launch> conv_server::admit_locked() {
             r->active_idx = (int)active.size();
             active.push_back(r);
         }
-        if (event_pool.empty()) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess)
-                event_pool.push_back(e);
-        }
-        if (!event_pool.empty()) {
-            L.ev = event_pool.back();
-            event_pool.pop_back();
-        }
+        L.token = next_token++;
         stats.max_bytes_in_flight = std::max<uint64_t>(stats.max_bytes_in_flight, bytes_in_flight);
         stats.max_slots_in_flight = std::max(stats.max_slots_in_flight, slots_in_flight);
         stats.max_batch = std::max(stats.max_batch, (int32_t)L.reqs.size());
@@ -287,8 +296,7 @@ std::vector<Launch> conv_server::admit_locked() {
 }
 
 // Enqueues one admitted group on its stream (no lock held).
-conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
-    if (!done_ev) return CONV_EHIP;
+conv_status conv_server::enqueue(Launch &L) {
     const int n = (int)L.reqs.size();
     hipStream_t s = streams[L.stream];
     if (n == 1) {
@@ -297,7 +305,8 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
         conv_status st = CONV_OK;
         if (r->ready && hipStreamWaitEvent(s, r->ready, 0) != hipSuccess) st = CONV_EHIP;
         if (st == CONV_OK) st = conv_sep5_1pass(r->in, r->out, r->k, &r->img, CONV_1PASS_FUSED, s);
-        if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
+        if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
+            st = CONV_EHIP;
         return st;
     }
     const int dtype = L.reqs[0]->img.dtype;
@@ -335,7 +344,8 @@ conv_status conv_server::enqueue(Launch &L, hipEvent_t done_ev) {
     for (auto &pe : last)
         if (st == CONV_OK && hipStreamWaitEvent(s, pe.second, 0) != hipSuccess) st = CONV_EHIP;
     if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
-    if (st == CONV_OK && hipEventRecord(done_ev, s) != hipSuccess) st = CONV_EHIP;
+    if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
+        st = CONV_EHIP;
     return st;
 }
 
@@ -354,9 +364,9 @@ bool conv_server::launched_locked(Launch &L, conv_status rc, uint64_t t_launch) 
         bytes_in_flight -= L.bytes;
         slots_in_flight -= (int)L.reqs.size();
         stream_busy[L.stream] = 0;
-        if (L.ev) event_pool.push_back(L.ev);
         return false;
     }
+    L.check_ns = t_launch + kStreamCheckNs;
     stats.launches += 1;
     int busy = 0;
     for (char b : stream_busy) busy += b != 0;
@@ -368,15 +378,26 @@ void conv_server::run() {
     hipSetDevice(device);
     uint64_t seen = ~0ull;  // seq when the locked part last ran
     for (;;) {
-        // 1. retire finished launches (event queries without the lock)
+        // 1. retire finished launches (completion words, without the lock)
         std::vector<std::pair<Launch, hipError_t>> finished;
         for (size_t i = 0; i < inflight.size();) {
-            const hipError_t q = hipEventQuery(inflight[i].ev);
+            Launch &L = inflight[i];
+            hipError_t q = __atomic_load_n(&done_host[L.stream * kDoneStride], __ATOMIC_ACQUIRE) >= L.token
+                               ? hipSuccess
+                               : hipErrorNotReady;
+            if (q == hipErrorNotReady) {
+                const uint64_t t = now_ns();
+                if (t >= L.check_ns) {
+                    // slow path: a failed launch never writes its token
+                    q = hipStreamQuery(streams[L.stream]);
+                    L.check_ns = t + kStreamCheckNs;
+                }
+            }
             if (q == hipErrorNotReady) {
                 ++i;
                 continue;
             }
-            finished.emplace_back(std::move(inflight[i]), q);
+            finished.emplace_back(std::move(L), q);
             inflight.erase(inflight.begin() + i);
         }
         const uint64_t t_done = now_ns();
@@ -396,7 +417,6 @@ void conv_server::run() {
                 bytes_in_flight -= L.bytes;
                 slots_in_flight -= (int)L.reqs.size();
                 stream_busy[L.stream] = 0;
-                event_pool.push_back(L.ev);
             }
             // launches made by submitters join the polled set
             for (Launch &L : handoff) inflight.push_back(std::move(L));
@@ -407,7 +427,7 @@ void conv_server::run() {
         // 3. launch (no lock)
         if (!admitted.empty()) {
             std::vector<conv_status> rc(admitted.size());
-            for (size_t i = 0; i < admitted.size(); ++i) rc[i] = enqueue(admitted[i], admitted[i].ev);
+            for (size_t i = 0; i < admitted.size(); ++i) rc[i] = enqueue(admitted[i]);
             const uint64_t t_launch = now_ns();
             std::lock_guard<std::mutex> g(mu);
             for (size_t i = 0; i < admitted.size(); ++i)
@@ -455,11 +475,25 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
     auto *s = new conv_server();
     s->cfg = *cfg;
     s->device = dev;
+    // one 64-byte line per stream's completion word
+    const size_t done_bytes = (size_t)cfg->n_streams * kDoneStride * sizeof(uint64_t);
+    e = hipHostMalloc((void **)&s->done_host, done_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        std::memset(s->done_host, 0, done_bytes);
+        e = hipHostGetDevicePointer((void **)&s->done_dev, s->done_host, 0);
+    }
+    if (e != hipSuccess) {
+        if (s->done_host) hipHostFree(s->done_host);
+        delete s;
+        hipSetDevice(prev);
+        return hip_error(e, "allocating the completion words");
+    }
     for (int i = 0; i < cfg->n_streams; ++i) {
         hipStream_t st = nullptr;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         if (e != hipSuccess) {
             for (hipStream_t x : s->streams) hipStreamDestroy(x);
+            hipHostFree(s->done_host);
             delete s;
             hipSetDevice(prev);
             return hip_error(e, "hipStreamCreate");
@@ -549,8 +583,9 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             // arrivals stay with the scheduler, which batches them.
             const uint64_t gap = std::min<uint64_t>(t_submit - srv->last_submit_ns, kGapClampNs);
             srv->gap_mean_ns = srv->gap_mean_ns - srv->gap_mean_ns / 4 + gap / 4;
+            // sparse on average and not inside a burst
             const bool try_direct = !srv->cfg.queue_only && srv->queue.empty() &&
-                                    srv->gap_mean_ns >= kDirectGapNs;
+                                    srv->gap_mean_ns >= kDirectGapNs && gap >= kDirectGapNs;
             srv->last_submit_ns = t_submit;
             srv->queue.push_back(r);
             srv->idle = false;
@@ -566,7 +601,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
         *ticket = r->ticket;
     }
     if (have_direct) {
-        const conv_status rc = srv->enqueue(direct, direct.ev);
+        const conv_status rc = srv->enqueue(direct);
         const uint64_t t_launch = now_ns();
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->launched_locked(direct, rc, t_launch)) {
@@ -624,9 +659,12 @@ conv_status conv_serve_destroy(conv_server *srv) {
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(srv->device);
-    for (hipEvent_t e : srv->event_pool) hipEventDestroy(e);
     for (hipEvent_t e : srv->ready_pool) hipEventDestroy(e);
-    for (hipStream_t s : srv->streams) hipStreamDestroy(s);
+    for (hipStream_t s : srv->streams) {
+        hipStreamSynchronize(s);
+        hipStreamDestroy(s);
+    }
+    hipHostFree(srv->done_host);
     hipSetDevice(prev);
     delete srv;  // the request pool's blocks go with it
     return CONV_OK;
