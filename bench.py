@@ -849,15 +849,22 @@ def main():
             fh.write(text + "\n")
     else:
         print("bench detail: " + text, file=sys.stderr, flush=True)
-    # the headline line stays short enough for a log tail: drop summary parts
-    # (they remain in the detail) until it fits
+    print(headline_text(line), flush=True)
+
+
+HEADLINE_MAX_CHARS = 4000
+
+
+def headline_text(line: dict) -> str:
+    """The headline line as JSON, short enough for a log tail: summary parts are
+    dropped (they remain in the detail output) until it fits."""
     out = json.dumps(line)
     for key in ("c5_640x480", "c4_us_per_image", "c1_us_per_call", "c5_mixed", "c3_batch64"):
-        if len(out) <= 4000:
+        if len(out) <= HEADLINE_MAX_CHARS:
             break
         line["summary"].pop(key, None)
         out = json.dumps(line)
-    print(out, flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -94,14 +94,15 @@ int main(void) {
         const double k64[5] = {k[0], k[1], k[2], k[3], k[4]};
         oracle_conv5_direct(a64, ref, k64, P, R, C, 1);
         const int exact = t == 0;
-        const char *names[4] = {"fused", "direct25", "2pass", "copy-back"};
-        for (int form = 0; form < 4; ++form) {
+        const char *names[5] = {"fused", "direct25", "2pass", "copy-back", "2pass-noalloc"};
+        for (int form = 0; form < 5; ++form) {
             HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st)); /* NaN pattern */
             conv_status rc;
             void *dst = d_out;
             if (form == 0) rc = conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_FUSED, st);
             else if (form == 1) rc = conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_DIRECT25, st);
             else if (form == 2) rc = conv_sep5_2pass(d_in, d_out, NULL, k, &img, st);
+            else if (form == 4) rc = conv_sep5_2pass_noalloc(d_in, d_out, k, &img, CONV_F32, st);
             else {
                 HIPCHECK(hipMemcpyAsync(d_cb, d_in, bytes, hipMemcpyDeviceToDevice, st));
                 rc = conv_sep5_1pass(d_cb, d_cb, k, &img, CONV_1PASS_FUSED, st);
@@ -115,6 +116,38 @@ int main(void) {
             printf("%-9s taps %d: max rel err %.3e\n", names[form], t, e);
             if (!(e <= 1e-6)) return fail(names[form]);
         }
+    }
+
+    /* the library's image copy moves every element unchanged */
+    {
+        HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+        if (conv_image_copy(d_in, d_out, &img, st) != CONV_OK) return fail("image copy");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+        if (memcmp(out, host, bytes) != 0) return fail("image copy differs from its input");
+        printf("image copy: OK\n");
+    }
+
+    /* the direct form's own tile configuration (kind 2): another band height
+       gives the same bits */
+    {
+        const float *k = tap_sets[1];
+        static float want[N];
+        conv_tile_cfg d0, c16 = {16, 1, 0, 8, 0};
+        if (conv_get_tile_cfg(CONV_F32, 2, &d0) != CONV_OK) return fail("get kind 2");
+        if (conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_DIRECT25, st) != CONV_OK)
+            return fail("direct25 default tiles");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(want, d_out, bytes, hipMemcpyDeviceToHost));
+        if (conv_set_tile_cfg(CONV_F32, 2, &c16) != CONV_OK) return fail("set kind 2");
+        HIPCHECK(hipMemsetAsync(d_out, 0xff, bytes, st));
+        if (conv_sep5_1pass(d_in, d_out, k, &img, CONV_1PASS_DIRECT25, st) != CONV_OK)
+            return fail("direct25 16-row bands");
+        HIPCHECK(hipStreamSynchronize(st));
+        HIPCHECK(hipMemcpy(out, d_out, bytes, hipMemcpyDeviceToHost));
+        if (conv_set_tile_cfg(CONV_F32, 2, &d0) != CONV_OK) return fail("restore kind 2");
+        if (memcmp(out, want, bytes) != 0) return fail("direct25 bits depend on the band height");
+        printf("direct25 with its own tiles: bitwise equal\n");
     }
 
     /* two images in one batch launch: the image and its first plane alone */
