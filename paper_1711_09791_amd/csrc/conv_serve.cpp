@@ -28,9 +28,9 @@
 //      skips the lock.
 // A submit that finds nothing queued and a stream idle launches its request
 // itself (unless queue_only is set) when submits arrive sparsely: the running
-// mean gap between submits is at least the time a launch takes to enqueue,
-// so there is nothing to batch with and the hop to the scheduler would only
-// add latency.  It hands the in-flight launch to the scheduler, which retires
+// mean gap between submits, and the gap before this one, are at least the
+// time a launch takes to enqueue, so there is nothing to batch with and the
+// hop to the scheduler would only add latency.  It hands the in-flight launch to the scheduler, which retires
 // it like its own.  Dense arrivals go to the scheduler, which batches them.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
@@ -38,11 +38,11 @@
 // identical.
 //
 // Locking: the mutex guards what submitters and pollers touch (queue, ticket
-// table, request pool, event pool, statistics) and the budget counters.
-// Streams and the list of in-flight launches belong to the scheduler thread,
-// and every HIP call of the scheduler runs without the lock.  Requests live in
-// a pool of fixed blocks and are found by ticket in a power-of-two table, so
-// a submit or a poll allocates nothing once the pool has warmed up.
+// table, request pool, producer-event pool, statistics) and the budget
+// counters.  Streams and the list of in-flight launches belong to the
+// scheduler thread, and every HIP call of the scheduler runs without the lock.
+// Requests live in a pool of fixed blocks and are found by ticket in a
+// power-of-two table: no heap allocation per request and no hashing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
