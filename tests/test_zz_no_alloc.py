@@ -111,3 +111,21 @@ def test_largest_fitting_intermediate():
     assert _noalloc(a, got, k, cs.CONV_F32) == cs.CONV_OK, cs.conv_last_error()
     torch.cuda.synchronize()
     assert torch.equal(_bits(got), _bits(ref))
+
+
+def test_takes_no_device_memory():
+    """Twenty calls on a 3 x 2048 x 2048 image (48 MiB of FP32 intermediate)
+    leave the device's free memory exactly as it was (hipMemGetInfo, read
+    through torch): no allocation, not even a stream-ordered one."""
+    torch = _torch()
+    k = synth.taps_random(81)
+    a = torch.rand(3, 2048, 2048, device="cuda")
+    out = torch.empty_like(a)
+    assert _noalloc(a, out, k, cs.CONV_F32) == cs.CONV_OK, cs.conv_last_error()  # first use on the device
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    for _ in range(20):
+        assert _noalloc(a, out, k, cs.CONV_F32) == cs.CONV_OK, cs.conv_last_error()
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 == free0, (free0, free1)
