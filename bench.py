@@ -536,12 +536,13 @@ def bench_serving(torch, cs, synth, args, sizes=None):
                 "throughput_req_per_s": (n - warm) / span, "offered_req_per_s": rate,
                 "submit_lag_p99_us": q(lg, 0.99) * 1e6, **extra}
 
-    def run_server(max_batch, n_streams, max_bytes, rate, n, warm, seed=5, queue_only=False):
+    def run_server(max_batch, n_streams, max_bytes, rate, n, warm, seed=5, queue_only=False, depth=1):
         arr, pin, pout, kk, imgs = requests(n, rate, seed)
         # inputs are static and synchronised: no producer ordering, like the
         # direct-launch baseline
         srv = cs.Server(budget, max_slots=NBUF, n_streams=n_streams, max_batch=max_batch,
-                        max_batch_bytes=max_bytes, producer_wait=False, queue_only=queue_only)
+                        max_batch_bytes=max_bytes, producer_wait=False, queue_only=queue_only,
+                        launch_depth=depth)
         tickets = (ctypes.c_uint64 * n)()
         lag = (ctypes.c_double * n)()
         check(cs, G.conv_loadgen_serve(srv._h, n, arr, pin, pout, kk, imgs, hs, tickets, lag))
@@ -580,6 +581,8 @@ def bench_serving(torch, cs, synth, args, sizes=None):
                                                               queue_only=True),
         "batched_count_cap_only": lambda rate, n, warm: run_server(16, 4, 0, rate, n, warm,
                                                                    queue_only=True),
+        "batched_depth_2": lambda rate, n, warm: run_server(16, 4, 128 * MB, rate, n, warm,
+                                                            queue_only=True, depth=2),
         "per_image_launch": lambda rate, n, warm: run_direct(1, rate, n, warm),
         "per_image_launch_4_streams": lambda rate, n, warm: run_direct(4, rate, n, warm),
     }

@@ -430,6 +430,12 @@ typedef struct {
                                   launch's enqueue time); dense arrivals go
                                   to the scheduler, which batches them;
                                   1: every launch is made by the scheduler */
+    int32_t launch_depth;      /* launches in flight per stream (0..4; 0 and
+                                  1: one, the next group is admitted when it
+                                  completes; 2..4: a group may also be
+                                  queued behind a running launch, so the
+                                  stream starts it without a host round
+                                  trip)                                     */
 } conv_serve_cfg;
 
 typedef struct {

@@ -51,7 +51,8 @@ class conv_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64),
-                ("producer_wait", ctypes.c_int32), ("queue_only", ctypes.c_int32)]
+                ("producer_wait", ctypes.c_int32), ("queue_only", ctypes.c_int32),
+                ("launch_depth", ctypes.c_int32)]
 
 
 class conv_req_times(ctypes.Structure):
@@ -527,10 +528,10 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                  max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                 producer_wait: bool = True, queue_only: bool = True):
+                 producer_wait: bool = True, queue_only: bool = True, launch_depth: int = 1):
         cfg = conv_serve_cfg(int(hbm_budget_bytes), int(max_slots), int(n_streams),
                              int(max_batch), int(device), int(max_batch_bytes),
-                             int(bool(producer_wait)), int(bool(queue_only)))
+                             int(bool(producer_wait)), int(bool(queue_only)), int(launch_depth))
         h = ctypes.c_void_p()
         _check(lib().conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -577,9 +578,10 @@ class Server:
 
 def conv_serve_create(hbm_budget_bytes: int, max_slots: int = 64, n_streams: int = 4,
                       max_batch: int = 16, device: int = -1, max_batch_bytes: int = 0,
-                      producer_wait: bool = True, queue_only: bool = True) -> Server:
+                      producer_wait: bool = True, queue_only: bool = True,
+                      launch_depth: int = 1) -> Server:
     return Server(hbm_budget_bytes, max_slots, n_streams, max_batch, device, max_batch_bytes,
-                  producer_wait, queue_only)
+                  producer_wait, queue_only, launch_depth)
 
 
 def conv_serve_submit(srv: Server, d_in, d_out, k, img=None, stream=None) -> int:

@@ -5,9 +5,11 @@
 // submitted without blocking into a host-side queue; the images stay in
 // device memory and only their descriptors pass through the queue.  One
 // scheduler thread per server loops over:
-//   1. retire: launches whose completion event has fired free their slots and
+//   1. retire: launches whose completion word holds their token free their slots and
 //      HBM budget and stamp their tickets done;
-//   2. admit: while a launch stream is idle, queued requests are taken in
+//   2. admit: while a launch stream has room (no launch, or with
+//      launch_depth > 1 fewer than that many, the last one already
+//      enqueued), queued requests are taken in
 //      arrival order as long as a slot is free and their footprint (input +
 //      output bytes) fits the budget, up to max_batch requests of one dtype
 //      and max_batch_bytes per launch (so large frames run alone and small
@@ -139,13 +141,18 @@ struct conv_server {
     std::vector<Req *> free_reqs;
     std::vector<Req *> table;            // ticket & (size - 1) -> live request
     std::vector<hipEvent_t> ready_pool;  // producer-stream events
-    // Completion words, one per stream (each stream runs one launch at a time),
-    // in pinned host memory: the stream writes a launch's token after its
-    // kernel; the scheduler reads them with plain loads.
+    // Completion words, one per stream, in pinned host memory: the stream
+    // writes a launch's token after its kernel; the scheduler reads them with
+    // plain loads.  Tokens grow in admission order and a stream's launches
+    // are enqueued in that order, so a word at or past a launch's token
+    // means that launch and every earlier one on the stream are done.
     uint64_t *done_host = nullptr;
     uint64_t *done_dev = nullptr;
     uint64_t next_token = 1;
-    std::vector<char> stream_busy;
+    int depth = 1;                       // launches in flight per stream, at most
+    std::vector<int> stream_load;        // launches admitted, not yet retired
+    std::vector<char> stream_pending;    // one of them not yet enqueued
+    std::vector<uint64_t> stream_bytes;  // their footprint
     std::vector<Launch> handoff;         // launched by a submitter, not yet polled
     uint64_t last_submit_ns = 0;
     uint64_t gap_mean_ns = kGapClampNs;  // running mean gap between submits
@@ -162,7 +169,7 @@ struct conv_server {
     std::thread th;
 
     void run();
-    std::vector<Launch> admit_locked();
+    std::vector<Launch> admit_locked(bool idle_only);
     bool blocked_locked(const Req *r, const Launch &L) const;
     void retire_locked(Req *r, int state, uint64_t t_done);
     conv_status enqueue(Launch &L);
@@ -245,16 +252,21 @@ bool conv_server::blocked_locked(const Req *r, const Launch &L) const {
     return false;
 }
 
-// Takes admissible requests off the queue (caller holds mu).
-std::vector<Launch> conv_server::admit_locked() {
+// Takes admissible requests off the queue (caller holds mu).  A group goes
+// to an idle stream, else (idle_only false, launch_depth > 1) behind the
+// launch with the fewest bytes on a stream with room whose launches are all
+// enqueued already, so that each stream receives its launches in token order.
+std::vector<Launch> conv_server::admit_locked(bool idle_only) {
     std::vector<Launch> out;
+    const int room = idle_only ? 1 : depth;
     while (!queue.empty()) {
         int s = -1;
-        for (int i = 0; i < (int)streams.size(); ++i)
-            if (!stream_busy[i]) {
+        for (int i = 0; i < (int)streams.size(); ++i) {
+            if (stream_pending[i] || stream_load[i] >= room) continue;
+            if (s < 0 || stream_load[i] < stream_load[s] ||
+                (stream_load[i] == stream_load[s] && stream_bytes[i] < stream_bytes[s]))
                 s = i;
-                break;
-            }
+        }
         if (s < 0) break;
         Launch L;
         L.stream = s;
@@ -276,7 +288,9 @@ std::vector<Launch> conv_server::admit_locked() {
         // the head does not fit yet, or must wait for an earlier request:
         // wait for a retirement
         if (L.reqs.empty()) break;
-        stream_busy[s] = 1;
+        stream_load[s] += 1;
+        stream_pending[s] = 1;
+        stream_bytes[s] += L.bytes;
         const uint64_t t = now_ns();
         for (Req *r : L.reqs) {
             r->t.admit_ns = t;
@@ -358,18 +372,20 @@ bool conv_server::launched_locked(Launch &L, conv_status rc, uint64_t t_launch) 
         r->ready = nullptr;
         r->t.launch_ns = t_launch;
     }
+    stream_pending[L.stream] = 0;
     if (rc != CONV_OK) {
         for (Req *r : L.reqs) retire_locked(r, FAILED, t_launch);
         stats.failed += L.reqs.size();
         bytes_in_flight -= L.bytes;
         slots_in_flight -= (int)L.reqs.size();
-        stream_busy[L.stream] = 0;
+        stream_load[L.stream] -= 1;
+        stream_bytes[L.stream] -= L.bytes;
         return false;
     }
     L.check_ns = t_launch + kStreamCheckNs;
     stats.launches += 1;
     int busy = 0;
-    for (char b : stream_busy) busy += b != 0;
+    for (int b : stream_load) busy += b;
     stats.max_streams_busy = std::max(stats.max_streams_busy, (int32_t)busy);
     return true;
 }
@@ -403,8 +419,12 @@ void conv_server::run() {
         const uint64_t t_done = now_ns();
         // Nothing finished and nothing submitted since the last look: the
         // queue cannot have become admissible, so poll again without mu.
+        // Every stream full of launches this thread polls: nothing can be
+        // admitted (and no submitter launch is pending) until one finishes.
         const uint64_t s_now = seq.load(std::memory_order_acquire);
-        if (finished.empty() && s_now == seen && !inflight.empty()) continue;
+        if (finished.empty() && !inflight.empty() &&
+            (s_now == seen || inflight.size() >= streams.size() * (size_t)depth))
+            continue;
         seen = s_now;
         std::vector<Launch> admitted;
         {
@@ -416,13 +436,14 @@ void conv_server::run() {
                 else stats.failed += L.reqs.size();
                 bytes_in_flight -= L.bytes;
                 slots_in_flight -= (int)L.reqs.size();
-                stream_busy[L.stream] = 0;
+                stream_load[L.stream] -= 1;
+                stream_bytes[L.stream] -= L.bytes;
             }
             // launches made by submitters join the polled set
             for (Launch &L : handoff) inflight.push_back(std::move(L));
             handoff.clear();
             // 2. admit
-            admitted = admit_locked();
+            admitted = admit_locked(false);
         }
         // 3. launch (no lock)
         if (!admitted.empty()) {
@@ -465,7 +486,8 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
     if (cfg->hbm_budget_bytes == 0 || cfg->max_slots < 1 || cfg->n_streams < 1 ||
         cfg->n_streams > 16 || cfg->max_batch < 1 ||
         (cfg->producer_wait != 0 && cfg->producer_wait != 1) ||
-        (cfg->queue_only != 0 && cfg->queue_only != 1))
+        (cfg->queue_only != 0 && cfg->queue_only != 1) || cfg->launch_depth < 0 ||
+        cfg->launch_depth > 4)
         return set_error(CONV_EINVAL, "bad server configuration");
     int prev = 0;
     hipGetDevice(&prev);
@@ -474,6 +496,7 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
     if (e != hipSuccess) return hip_error(e, "hipSetDevice");
     auto *s = new conv_server();
     s->cfg = *cfg;
+    s->depth = cfg->launch_depth > 1 ? cfg->launch_depth : 1;
     s->device = dev;
     // one 64-byte line per stream's completion word
     const size_t done_bytes = (size_t)cfg->n_streams * kDoneStride * sizeof(uint64_t);
@@ -499,7 +522,9 @@ conv_status conv_serve_create(const conv_serve_cfg *cfg, conv_server **srv) {
             return hip_error(e, "hipStreamCreate");
         }
         s->streams.push_back(st);
-        s->stream_busy.push_back(0);
+        s->stream_load.push_back(0);
+        s->stream_pending.push_back(0);
+        s->stream_bytes.push_back(0);
     }
     hipSetDevice(prev);
     s->th = std::thread([s] { s->run(); });
@@ -591,7 +616,7 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
             srv->idle = false;
             srv->seq.fetch_add(1, std::memory_order_release);
             if (try_direct && on_device) {
-                std::vector<Launch> now = srv->admit_locked();
+                std::vector<Launch> now = srv->admit_locked(true);
                 if (!now.empty()) {
                     direct = std::move(now[0]);
                     have_direct = true;

@@ -213,7 +213,9 @@ def test_serve_config_validation():
                 cs.conv_serve_cfg(1 << 30, 4, 17, 8, -1, 0, 1),
                 cs.conv_serve_cfg(1 << 30, 4, 2, 0, -1, 0, 1),
                 cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 2),
-                cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 1, 2)):   # queue_only is 0 or 1
+                cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 1, 2),    # queue_only is 0 or 1
+                cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 1, 1, -1),  # launch_depth is 0..4
+                cs.conv_serve_cfg(1 << 30, 4, 2, 8, -1, 0, 1, 1, 5)):
         assert L.conv_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == cs.CONV_EINVAL
     assert L.conv_serve_poll(None, 1, None) == cs.CONV_EINVAL
     assert L.conv_serve_destroy(None) == cs.CONV_OK

@@ -38,10 +38,11 @@ def _wait_all(srv, tickets, timeout_s=60.0):
     return done
 
 
-@pytest.mark.parametrize("queue_only", [False, True])
-def test_results_alone_equal_results_in_the_mix(queue_only):
+@pytest.mark.parametrize("queue_only,depth", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_results_alone_equal_results_in_the_mix(queue_only, depth):
     """queue_only = False: submits that find nothing queued and a stream idle
-    launch their request themselves; True: every launch by the scheduler."""
+    launch their request themselves; True: every launch by the scheduler.
+    depth 2: a group may be queued behind a running launch on its stream."""
     import torch
 
     torch.manual_seed(0)
@@ -54,7 +55,7 @@ def test_results_alone_equal_results_in_the_mix(queue_only):
     torch.cuda.synchronize()
     budget = 600 << 20
     srv = cs.conv_serve_create(budget, max_slots=16, n_streams=4, max_batch=8,
-                               queue_only=queue_only)
+                               queue_only=queue_only, launch_depth=depth)
     try:
         outs = [gu.nan_like(a) for a, _ in reqs]
         tickets = []
@@ -157,8 +158,8 @@ def test_mixed_dtypes_ragged_and_empty(queue_only):
             gu.gate16(got, ref, dt)
 
 
-@pytest.mark.parametrize("queue_only", [False, True])
-def test_concurrent_submitters(queue_only):
+@pytest.mark.parametrize("queue_only,depth", [(False, 1), (True, 1), (False, 2)])
+def test_concurrent_submitters(queue_only, depth):
     """Four host threads submit to one server at once (ctypes releases the GIL
     during each call, so submits, launches from submit and the scheduler's
     polling interleave): every request completes once and equals the lone
@@ -181,7 +182,7 @@ def test_concurrent_submitters(queue_only):
     outs = [gu.nan_like(a) for a, _ in reqs]
     torch.cuda.synchronize()
     srv = cs.conv_serve_create(1 << 30, max_slots=16, n_streams=3, max_batch=6,
-                               queue_only=queue_only)
+                               queue_only=queue_only, launch_depth=depth)
     tickets = [None] * len(reqs)
     errors = []
 
@@ -305,8 +306,8 @@ def test_no_producer_wait_mode_after_sync():
         assert torch.equal(o, r)
 
 
-@pytest.mark.parametrize("queue_only", [False, True])
-def test_overlapping_requests_run_in_submission_order(queue_only):
+@pytest.mark.parametrize("queue_only,depth", [(False, 1), (True, 1), (True, 2)])
+def test_overlapping_requests_run_in_submission_order(queue_only, depth):
     """Requests whose buffers overlap, queued together behind a large request
     where the scheduler would batch them: a chained pair (B reads A's output),
     a shared output (D writes C's output), a write over an earlier request's
@@ -351,7 +352,7 @@ def test_overlapping_requests_run_in_submission_order(queue_only):
     torch.cuda.synchronize()
 
     srv = cs.conv_serve_create(1 << 33, max_slots=32, n_streams=2, max_batch=8,
-                               queue_only=queue_only)
+                               queue_only=queue_only, launch_depth=depth)
     try:
         tickets = [srv.submit(blocker, blocker_out, ks[15])]
         order = [(x, y, ks[0]), (y, z, ks[1]), (p, q, ks[2]), (r, q, ks[3]),
@@ -375,3 +376,39 @@ def test_overlapping_requests_run_in_submission_order(queue_only):
     for o, e in zip(other_outs, exp_others):
         assert torch.equal(o, e)
     print("serve stats (overlapping requests)", st)
+
+
+def test_launch_queued_behind_a_running_one():
+    """launch_depth 2 on one stream: while a large request runs, the next group
+    is enqueued behind it (two launches in flight on the one stream), and the
+    completion word retires each launch only after its own kernel: every result
+    equals its lone call, and the later requests are not reported done before
+    the large one they queue behind."""
+    import torch
+
+    big = torch.rand(3, 4096, 8192, device="cuda")
+    big_out = gu.nan_like(big)
+    small = _requests(10, seed=41)
+    small_outs = [gu.nan_like(a) for a, _ in small]
+    kb = synth.taps_random(9400)
+    torch.cuda.synchronize()
+    srv = cs.conv_serve_create(1 << 33, max_slots=16, n_streams=1, max_batch=4, launch_depth=2)
+    try:
+        tickets = [srv.submit(big, big_out, kb)]
+        tickets += [srv.submit(a, o, k) for (a, k), o in zip(small, small_outs)]
+        times = _wait_all(srv, tickets)
+        st = srv.stats()
+    finally:
+        srv.destroy()
+    assert st["failed"] == 0 and st["completed"] == len(tickets)
+    assert st["max_streams_busy"] == 2, st
+    t_big = times[tickets[0]]
+    for t in tickets[1:]:
+        assert times[t]["done_ns"] >= t_big["done_ns"]
+    ref = gu.nan_like(big)
+    cs.conv_sep5_1pass(big, ref, kb)
+    assert torch.equal(big_out, ref)
+    for (a, k), o in zip(small, small_outs):
+        r = gu.nan_like(a)
+        cs.conv_sep5_1pass(a, r, k)
+        assert torch.equal(o, r)
