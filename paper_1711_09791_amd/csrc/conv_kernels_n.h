@@ -178,12 +178,88 @@ __device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], 
     }
 }
 
+// The same tree for n = 9 with two changes that leave every operation and its
+// order as above: leaf a reads its n weights from LDS just before its chains
+// (81 weights next to the descriptor do not fit the scalar registers, and
+// parking them in vector lanes cost one read-back per ~8 multiply-adds), and
+// the window rows are decoded when first needed (row i at leaf i-TH+1), so
+// that only about TH decoded rows are live instead of TH+2R.  Scheduling
+// barriers do not hold pure arithmetic in place, so each leaf's results pass
+// through empty asm statements chained on a token, and the next leaf's weight
+// address and raw row through one that consumes the token: no value changes,
+// but nothing of leaf a can be hoisted above the end of leaf a-1.
+template <class D, int R>
+__device__ __forceinline__ void after(RawN<D, true, R> &r, float dep) {
+    asm volatile("" : "+v"(r.m) : "v"(dep));
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(r.h) / sizeof(r.h[0])); ++j) asm volatile("" : "+v"(r.h[j]) : "v"(dep));
+}
+template <class D, int R>
+__device__ __forceinline__ void after(RawN<D, false, R> &r, float dep) {
+#pragma unroll
+    for (int e = 0; e < D::VEC + 2 * R; ++e) asm volatile("" : "+v"(r.e[e]) : "v"(dep));
+}
+
+template <int LO, int HI, int NT_, int TH, int VEC, int WN, class RawRow, class Dec>
+__device__ __forceinline__ void direct_tree_lds(RawRow (&raw)[TH + NT_ - 1],
+                                                float (&w)[TH + NT_ - 1][WN], const Dec &decode,
+                                                uint32_t kaddr, float &dep, float (&s)[TH][VEC]) {
+    if constexpr (HI - LO == 1) {
+        constexpr int a = LO;
+        if constexpr (a == 0) {
+#pragma unroll
+            for (int i = 0; i < TH - 1; ++i) decode(raw[i], w[i]);
+        }
+        after(raw[a + TH - 1], dep);
+        decode(raw[a + TH - 1], w[a + TH - 1]);
+        asm volatile("" : "+v"(kaddr) : "v"(dep));
+        const __attribute__((address_space(3))) float *Kl =
+            (const __attribute__((address_space(3))) float *)(uintptr_t)kaddr;
+        float k[NT_];
+#pragma unroll
+        for (int b = 0; b < NT_; ++b) k[b] = Kl[a * NT_ + b];
+#pragma unroll
+        for (int j = 0; j < TH; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[j][e] = w[j + a][e] * k[0];
+#pragma unroll
+        for (int b = 1; b < NT_; ++b) {
+#pragma unroll
+            for (int j = 0; j < TH; ++j)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s[j][e] = __builtin_fmaf(w[j + a][e + b], k[b], s[j][e]);
+        }
+        // the token depends on every result of this leaf
+#pragma unroll
+        for (int j = 0; j < TH; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(s[j][e]), "+v"(dep));
+    } else {
+        constexpr int n = HI - LO;
+        constexpr int half = n >= 8 ? (n > 8 ? 8 : 4) : (n > 4 ? 4 : (n > 2 ? 2 : 1));
+        float r[TH][VEC];
+        direct_tree_lds<LO, LO + half, NT_, TH, VEC, WN>(raw, w, decode, kaddr, dep, s);
+        direct_tree_lds<LO + half, HI, NT_, TH, VEC, WN>(raw, w, decode, kaddr, dep, r);
+#pragma unroll
+        for (int j = 0; j < TH; ++j)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[j][e] = s[j][e] + r[j][e];
+    }
+}
+
+// Weights of the direct form come from LDS for n = 9 (see direct_tree_lds):
+// 148 us against 169 us per 3x4096x4096 FP32 image, bitwise equal.  At n = 7
+// the same change cost occupancy (170 VGPRs against 115, whose 17 spilled
+// SGPRs are cheap) and ran 121 us against 108 us; 2-row bands were slower at
+// both widths.
+template <int R, int MODE> constexpr bool direct_lds() { return MODE == MODE_DIRECT25 && R >= 4; }
+
 // ---- one band ---------------------------------------------------------------------
 // MODE: MODE_FUSED (separable, register window), MODE_DIRECT25 (direct n x n
 // with tp.K), MODE_ROWPASS / MODE_COLPASS (two-pass kernels).
 template <class D, bool AL, int R, int MODE, bool EDGE, int TH, int SAUX = NT>
-__device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int plane, int xs, int y0,
-                                       int y1, int lane) {
+__device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, const float *Kl, int plane,
+                                       int xs, int y0, int y1, int lane) {
     constexpr int VEC = D::VEC;
     constexpr int NT_ = 2 * R + 1;
     const int H = im.rows, W = im.cols;
@@ -245,6 +321,14 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
                 issue_n<D, R>(raw[i], p, sbytes, x, hoff);
         }
         float w[TH + 2 * R][WN];
+        float dsum[DIRECT ? TH : 1][VEC];
+        if constexpr (direct_lds<R, MODE>()) {
+            const auto dec_row = [](const RawIn &r, float (&v)[WN]) { decode_n<D, R>(r, v); };
+            float dep = 0.0f;
+            direct_tree_lds<0, NT_, NT_, TH, VEC, WN>(
+                raw, w, dec_row, (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl,
+                dep, dsum);
+        } else {
 #pragma unroll
         for (int i = 0; i < TH + 2 * R; ++i) {
             if constexpr (COL) {
@@ -258,8 +342,8 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
                 hfilter_n<VEC, R>(v, tp.k, w[i]);
             }
         }
-        float dsum[DIRECT ? TH : 1][VEC];
         if constexpr (DIRECT) direct_tree<0, NT_, NT_, TH, VEC, WN>(w, tp.K, dsum);
+        }
 #pragma unroll
         for (int j = 0; j < TH; ++j) {
             const int y = y0 + j;
@@ -287,8 +371,8 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, int pl
 }
 
 template <class D, bool AL, int R, int MODE, int WAVES, int TH, int SAUX = NT>
-__device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, int64_t lt, int wave,
-                                           int lane) {
+__device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, const float *Kl,
+                                           int64_t lt, int wave, int lane) {
     const int sg = (int)(lt % im.nsg);
     const int64_t t = lt / im.nsg;
     const int band = (int)(t % im.nb);
@@ -301,9 +385,9 @@ __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, in
     const bool col_edge = xs < R || xs + WAVE * D::VEC > im.cols - R;
     const bool row_edge = MODE != MODE_ROWPASS && (y0 < R || y0 + TH > im.rows - R);
     if (col_edge || row_edge)
-        band_n<D, AL, R, MODE, true, TH, SAUX>(im, tp, plane, xs, y0, y1, lane);
+        band_n<D, AL, R, MODE, true, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
     else
-        band_n<D, AL, R, MODE, false, TH, SAUX>(im, tp, plane, xs, y0, y1, lane);
+        band_n<D, AL, R, MODE, false, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
 }
 
 // One workgroup per logical tile (grids above 2^20 workgroups loop); with
@@ -313,6 +397,14 @@ template <class D, bool AL, int R, int MODE, int WAVES, int TH, int SAUX = NT>
 __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, int64_t nblocks) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const float *Kl = nullptr;
+    if constexpr (direct_lds<R, MODE>()) {
+        constexpr int NK = (2 * R + 1) * (2 * R + 1);
+        __shared__ float sK[NK];
+        for (int i = threadIdx.x; i < NK; i += WAVE * WAVES) sK[i] = tp.K[i];
+        __syncthreads();
+        Kl = sK;
+    }
     for (int64_t base = 0; base < nblocks; base += gridDim.x) {
         const int64_t left = nblocks - base;
         const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
@@ -320,7 +412,7 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, in
         const int b = im.xcd_slabs > 1
                           ? xcd_chunk_remap(blockIdx.x, cnt, (int64_t)im.xcd_slabs * im.nsg)
                           : (int)blockIdx.x;
-        run_tile_n<D, AL, R, MODE, WAVES, TH, SAUX>(im, tp, base + b, wave, lane);
+        run_tile_n<D, AL, R, MODE, WAVES, TH, SAUX>(im, tp, Kl, base + b, wave, lane);
     }
 }
 
