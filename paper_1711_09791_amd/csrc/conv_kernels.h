@@ -41,6 +41,7 @@
 
 #include "conv_internal.h"
 
+#include <cstring>
 #include <type_traits>
 
 namespace convsep5 {
@@ -1055,18 +1056,105 @@ __device__ __forceinline__ int64_t chunk_tiles(const ImgDev &im) {
     return (int64_t)im.xcd_slabs * im.nsg;
 }
 
+// Kernel argument of a single-image launch.  The runtime's host cost per
+// launch steps up above 112 argument bytes (MI355X: about 2.9 against
+// 3.8-4.1 us per launch), and a kernel that reads gridDim receives 256 more
+// bytes of hidden arguments.  So the launch passes its grid size, leaves out
+// what the kernel recomputes (strips, strip groups, bands) and the batch's
+// tile range, and carries the 25 weights of the direct form only for that
+// form: 96 bytes, 200 with the weights.
+struct ImgArg {
+    const void *in;
+    void *out;
+    float *tmp;
+    int64_t pitch, pstride, nblocks;
+    int32_t planes, rows, cols, grid;
+    int16_t th, xcd_slabs;
+    int8_t keep_out, tq, pk32, pk16;
+    float k[5];
+};
+struct ImgArgK : ImgArg {
+    float K[25];
+};
+static_assert(sizeof(ImgArg) <= 96, "single-image kernel argument above 96 bytes");
+template <int MODE>
+using ImgArgOf = typename std::conditional<MODE == MODE_DIRECT25, ImgArgK, ImgArg>::type;
+
+template <int MODE>
+inline ImgArgOf<MODE> image_arg(const ImgDev &im, int64_t nblocks, int grid) {
+    ImgArgOf<MODE> a;
+    std::memset(&a, 0, sizeof a);
+    a.in = im.in;
+    a.out = im.out;
+    a.tmp = im.tmp;
+    a.pitch = im.pitch;
+    a.pstride = im.pstride;
+    a.nblocks = nblocks;
+    a.planes = im.planes;
+    a.rows = im.rows;
+    a.cols = im.cols;
+    a.grid = grid;
+    a.th = (int16_t)im.th;
+    a.xcd_slabs = (int16_t)im.xcd_slabs;
+    a.keep_out = (int8_t)im.keep_out;
+    a.tq = (int8_t)im.tq;
+    a.pk32 = (int8_t)im.pk32;
+    a.pk16 = (int8_t)im.pk16;
+    for (int i = 0; i < 5; ++i) a.k[i] = im.tp.k[i];
+    if constexpr (MODE == MODE_DIRECT25)
+        for (int i = 0; i < 25; ++i) a.K[i] = im.tp.K[i];
+    return a;
+}
+
+// The descriptor a tile reads, rebuilt from the kernel argument (uniform
+// values, held in scalar registers).
+template <class D, bool AL, int MODE, int WAVES>
+__device__ __forceinline__ ImgDev image_of_arg(const ImgArgOf<MODE> &a) {
+    ImgDev d;
+    d.in = a.in;
+    d.out = a.out;
+    d.tmp = a.tmp;
+    d.pitch = a.pitch;
+    d.pstride = a.pstride;
+    d.planes = a.planes;
+    d.rows = a.rows;
+    d.cols = a.cols;
+    d.aligned = AL ? 1 : 0;
+    d.ns = (a.cols + WAVE * D::VEC - 1) / (WAVE * D::VEC);
+    d.nsg = (d.ns + WAVES - 1) / WAVES;
+    d.th = a.th;
+    d.nb = (a.rows + a.th - 1) / a.th;
+    d.xcd_slabs = a.xcd_slabs;
+    d.keep_out = a.keep_out;
+    d.tq = a.tq;
+    d.pk32 = a.pk32;
+    d.pk16 = a.pk16;
+    d.tile_begin = 0;
+    d.tile_end = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) d.tp.k[i] = a.k[i];
+    if constexpr (MODE == MODE_DIRECT25) {
+#pragma unroll
+        for (int i = 0; i < 25; ++i) d.tp.K[i] = a.K[i];
+    }
+    return d;
+}
+
 // One workgroup per logical tile; grids above 2^20 workgroups loop.  In
 // launch order (xcd_slabs = 0) the resident waves sweep the image row-band by
 // row-band; with xcd_slabs = 1 each XCD walks its own slab of full rows; with
 // xcd_slabs = c >= 2 the XCDs take turns on chunks of c band rows.  SAUX is
 // the cache policy of the output stores.
 template <class D, bool AL, int MODE, int WAVES, int TH, int SAUX = NT, bool PK = false>
-__global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgDev im, int64_t nblocks) {
+__global__ __launch_bounds__(WAVE *WAVES) void k_image(ImgArgOf<MODE> arg) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    for (int64_t base = 0; base < nblocks; base += gridDim.x) {
+    const ImgDev im = image_of_arg<D, AL, MODE, WAVES>(arg);
+    const int64_t nblocks = arg.nblocks;
+    const int grid = arg.grid;
+    for (int64_t base = 0; base < nblocks; base += grid) {
         const int64_t left = nblocks - base;
-        const int cnt = left < (int64_t)gridDim.x ? (int)left : (int)gridDim.x;
+        const int cnt = left < (int64_t)grid ? (int)left : grid;
         if ((int)blockIdx.x >= cnt) break;
         const int b = im.xcd_slabs == 1   ? xcd_remap(blockIdx.x, cnt)
                       : im.xcd_slabs > 1 ? xcd_chunk_remap(blockIdx.x, cnt, chunk_tiles<PK>(im))
@@ -1164,30 +1252,31 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_batch_args(BatchArgs) {
 
 // ---- launchers -------------------------------------------------------------------
 template <class D, bool AL, int MODE, int WAVES, int SAUX>
-hipError_t launch_image_th_p(const ImgDev &im, int64_t nblocks, hipStream_t s) {
+hipError_t launch_image_th_p(const ImgDev &im_, int64_t nblocks, hipStream_t s) {
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     const dim3 blk(WAVE * WAVES);
-    const bool pk = im.tq > 1;
+    const bool pk = im_.tq > 1;
+    const ImgArgOf<MODE> im = image_arg<MODE>(im_, nblocks, grid);
     switch (im.th) {
     case 4:
         if constexpr (packs<D, AL, MODE, WAVES, 4>()) {
             if (pk) {
-                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX, true>), dim3(grid), blk, 0, s, im, nblocks);
+                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX, true>), dim3(grid), blk, 0, s, im);
                 break;
             }
         }
-        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX>), dim3(grid), blk, 0, s, im, nblocks);
+        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 4, SAUX>), dim3(grid), blk, 0, s, im);
         break;
     case 8:
         if constexpr (packs<D, AL, MODE, WAVES, 8>()) {
             if (pk) {
-                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX, true>), dim3(grid), blk, 0, s, im, nblocks);
+                hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX, true>), dim3(grid), blk, 0, s, im);
                 break;
             }
         }
-        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX>), dim3(grid), blk, 0, s, im, nblocks);
+        hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 8, SAUX>), dim3(grid), blk, 0, s, im);
         break;
-    default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0, SAUX>), dim3(grid), blk, 0, s, im, nblocks); break;
+    default: hipLaunchKernelGGL((k_image<D, AL, MODE, WAVES, 0, SAUX>), dim3(grid), blk, 0, s, im); break;
     }
     return hipGetLastError();
 }
