@@ -32,8 +32,8 @@
 // itself (unless queue_only is set) when submits arrive sparsely: the running
 // mean gap between submits, and the gap before this one, are at least the
 // time a launch takes to enqueue, so there is nothing to batch with and the
-// hop to the scheduler would only add latency.  It hands the in-flight launch to the scheduler, which retires
-// it like its own.  Dense arrivals go to the scheduler, which batches them.
+// hop to the scheduler would only add latency.  It hands the in-flight launch to the scheduler, which writes
+// its completion token (with one launch per stream) and retires it like its own.  Dense arrivals go to the scheduler, which batches them.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
 // same tile code on the same values as a lone call, so it is bitwise
@@ -119,6 +119,7 @@ struct Launch {
     uint64_t token = 0;    // written to its stream's completion word after the kernel
     uint64_t check_ns = 0; // next time to ask hipStreamQuery about it
     int stream = 0;
+    bool token_pending = false;  // launched by a submitter: the scheduler writes its token
 };
 
 }  // namespace
@@ -172,7 +173,7 @@ struct conv_server {
     std::vector<Launch> admit_locked(bool idle_only);
     bool blocked_locked(const Req *r, const Launch &L) const;
     void retire_locked(Req *r, int state, uint64_t t_done);
-    conv_status enqueue(Launch &L);
+    conv_status enqueue(Launch &L, bool write_token = true);
     bool launched_locked(Launch &L, conv_status rc, uint64_t t_launch);
     Req *new_req_locked();
     void put_ticket_locked(Req *r);
@@ -310,7 +311,7 @@ std::vector<Launch> conv_server::admit_locked(bool idle_only) {
 }
 
 // Enqueues one admitted group on its stream (no lock held).
-conv_status conv_server::enqueue(Launch &L) {
+conv_status conv_server::enqueue(Launch &L, bool write_token) {
     const int n = (int)L.reqs.size();
     hipStream_t s = streams[L.stream];
     if (n == 1) {
@@ -319,7 +320,8 @@ conv_status conv_server::enqueue(Launch &L) {
         conv_status st = CONV_OK;
         if (r->ready && hipStreamWaitEvent(s, r->ready, 0) != hipSuccess) st = CONV_EHIP;
         if (st == CONV_OK) st = conv_sep5_1pass(r->in, r->out, r->k, &r->img, CONV_1PASS_FUSED, s);
-        if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
+        if (st == CONV_OK && !write_token) L.token_pending = true;
+        else if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
             st = CONV_EHIP;
         return st;
     }
@@ -358,7 +360,8 @@ conv_status conv_server::enqueue(Launch &L) {
     for (auto &pe : last)
         if (st == CONV_OK && hipStreamWaitEvent(s, pe.second, 0) != hipSuccess) st = CONV_EHIP;
     if (st == CONV_OK) st = enqueue_batch(descs, total, dtype, MODE_FUSED, tc, s);
-    if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
+    if (st == CONV_OK && !write_token) L.token_pending = true;
+    else if (st == CONV_OK && hipStreamWriteValue64(s, &done_dev[L.stream * kDoneStride], L.token, 0) != hipSuccess)
         st = CONV_EHIP;
     return st;
 }
@@ -445,6 +448,15 @@ void conv_server::run() {
             // 2. admit
             admitted = admit_locked(false);
         }
+        // A submitter's launch leaves its token to this thread (the submitting
+        // thread then spends only the kernel launch).  Its stream takes no
+        // other launch before this one retires (one launch per stream), and
+        // the kernel outlasts the hand-off, so the token still follows it.
+        for (Launch &L : inflight)
+            if (L.token_pending) {
+                (void)hipStreamWriteValue64(streams[L.stream], &done_dev[L.stream * kDoneStride], L.token, 0);
+                L.token_pending = false;
+            }
         // 3. launch (no lock)
         if (!admitted.empty()) {
             std::vector<conv_status> rc(admitted.size());
@@ -626,7 +638,8 @@ conv_status conv_serve_submit(conv_server *srv, const void *d_in, void *d_out, c
         *ticket = r->ticket;
     }
     if (have_direct) {
-        const conv_status rc = srv->enqueue(direct);
+        // with one launch per stream the scheduler writes the launch's token
+        const conv_status rc = srv->enqueue(direct, /*write_token=*/srv->depth > 1);
         const uint64_t t_launch = now_ns();
         std::lock_guard<std::mutex> g(srv->mu);
         if (srv->launched_locked(direct, rc, t_launch)) {
