@@ -5,13 +5,13 @@
 // submitted without blocking into a host-side queue; the images stay in
 // device memory and only their descriptors pass through the queue.  One
 // scheduler thread per server loops over:
-//   1. retire: launches whose completion word holds their token free their slots and
-//      HBM budget and stamp their tickets done;
+//   1. retire: launches whose completion word holds their token free their
+//      slots and HBM budget and stamp their tickets done;
 //   2. admit: while a launch stream has room (no launch, or with
 //      launch_depth > 1 fewer than that many, the last one already
-//      enqueued), queued requests are taken in
-//      arrival order as long as a slot is free and their footprint (input +
-//      output bytes) fits the budget, up to max_batch requests of one dtype
+//      enqueued), queued requests are taken in arrival order as long as a
+//      slot is free and their footprint (input + output bytes) fits the
+//      budget, up to max_batch requests of one dtype
 //      and max_batch_bytes per launch (so large frames run alone and small
 //      ones share launches).  A request whose buffers overlap those of a
 //      request admitted before it and not yet retired (it reads what that one
@@ -32,8 +32,10 @@
 // itself (unless queue_only is set) when submits arrive sparsely: the running
 // mean gap between submits, and the gap before this one, are at least the
 // time a launch takes to enqueue, so there is nothing to batch with and the
-// hop to the scheduler would only add latency.  It hands the in-flight launch to the scheduler, which writes
-// its completion token (with one launch per stream) and retires it like its own.  Dense arrivals go to the scheduler, which batches them.
+// hop to the scheduler would only add latency.  It hands the in-flight launch
+// to the scheduler, which writes its completion token (with one launch per
+// stream) and retires it like its own.  Dense arrivals go to the scheduler,
+// which batches them.
 // Requests that arrive while a launch runs go into the next launch on another
 // stream, so their work overlaps on the device.  A request's result is the
 // same tile code on the same values as a lone call, so it is bitwise
