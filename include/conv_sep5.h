@@ -85,7 +85,9 @@ typedef enum { CONV_F32 = 0, CONV_F16 = 1, CONV_BF16 = 2 } conv_dtype;
  * The fast path needs 16-byte aligned base pointers and cols, pitch and
  * plane_stride (HWC: cols*planes and pitch) that are multiples of
  * 16/sizeof(element); other layouts run a slower element-wise path with
- * identical results.
+ * identical results.  Rows that start on a 128-byte line run fastest (each
+ * wave reads and writes 1 KB of a row): a pitch of a multiple of 128 bytes
+ * gives that for every row.
  */
 typedef struct {
     int32_t planes;
