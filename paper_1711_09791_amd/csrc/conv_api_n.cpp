@@ -23,9 +23,9 @@ conv_status check_width(int32_t n) {
 // Descriptor of one width-n launch: the row-band height and workgroup width
 // are fixed per dtype and form; the width-5 taps inside stay unused.
 int64_t fill_desc_n(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
-                    const Layout &L, bool direct) {
+                    const Layout &L, bool direct, int radius) {
     conv_tile_cfg cfg{};
-    cfg.rows_per_tile = direct ? kThDirectN : kThSepN;
+    cfg.rows_per_tile = direct ? th_direct_n(img->dtype == CONV_F32, radius) : kThSepN;
     cfg.waves_per_wg = waves_n(img->dtype);
     cfg.xcd_slabs = kXcdChunkRowsN / cfg.rows_per_tile;
     return fill_desc(d, in, out, tmp, img, L, kNoTaps, cfg);
@@ -46,7 +46,7 @@ conv_status run_single(const void *d_in, void *d_out, const TapsN &tp, int n,
     const int radius = n / 2;
     ImgDev d;
     if (d_in != (const void *)d_out) {
-        const int64_t nblocks = fill_desc_n(&d, d_in, d_out, nullptr, img, L, direct);
+        const int64_t nblocks = fill_desc_n(&d, d_in, d_out, nullptr, img, L, direct, radius);
         const hipError_t e = launch_image_n(d, tp, img->dtype, radius, kmode, nblocks, stream);
         return e == hipSuccess ? CONV_OK : hip_error(e, "width-n kernel launch");
     }
@@ -55,7 +55,7 @@ conv_status run_single(const void *d_in, void *d_out, const TapsN &tp, int n,
     if (e != hipSuccess)
         return set_error(CONV_ENOMEM, "hipMallocAsync(%lld): %s", (long long)L.extent_bytes,
                          hipGetErrorString(e));
-    int64_t nblocks = fill_desc_n(&d, d_in, scratch, nullptr, img, L, direct);
+    int64_t nblocks = fill_desc_n(&d, d_in, scratch, nullptr, img, L, direct, radius);
     d.keep_out = 1;  // cached stores: the copy reads the scratch next
     e = launch_image_n(d, tp, img->dtype, radius, kmode, nblocks, stream);
     if (e == hipSuccess) e = launch_copy(scratch, d_out, img, L,
@@ -134,7 +134,7 @@ conv_status conv_sepn_2pass(const void *d_in, void *d_out, float *d_tmp, const f
     TapsN tp;
     fill_taps_sep(&tp, k, n);
     ImgDev d;
-    const int64_t nblocks = fill_desc_n(&d, d_in, d_out, tmp, img, L, false);
+    const int64_t nblocks = fill_desc_n(&d, d_in, d_out, tmp, img, L, false, n / 2);
     e = launch_image_n(d, tp, img->dtype, n / 2, MODE_ROWPASS, nblocks, stream);
     if (e == hipSuccess) e = launch_image_n(d, tp, img->dtype, n / 2, MODE_COLPASS, nblocks, stream);
     if (!d_tmp) (void)hipFreeAsync(tmp, stream);

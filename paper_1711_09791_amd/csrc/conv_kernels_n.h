@@ -9,8 +9,9 @@
 // buffer load per lane per row, R-column halos from neighbouring lanes by DPP,
 // per-row buffer resources so that lanes past the edge read 0 and drop their
 // stores.  Every band is fully unrolled: all TH+2R input rows are issued
-// first; a short last band computes TH rows and stores only its own.  The
-// output frame of R pixels is written as +0.0.
+// first; a short last band computes TH rows and stores only its own (the FP32
+// direct form at n >= 7 walks 16-row bands instead, loading rows as it goes).
+// The output frame of R pixels is written as +0.0.
 //
 // Arithmetic (fixed for every tile shape):
 //   horizontal  h = v[x-R]*k0; h = fma(v[x-R+1], k1, h); ... (n taps)
@@ -247,12 +248,150 @@ __device__ __forceinline__ void direct_tree_lds(RawRow (&raw)[TH + NT_ - 1],
     }
 }
 
-// Weights of the direct form come from LDS for n = 9 (see direct_tree_lds):
-// 148 us against 169 us per 3x4096x4096 FP32 image, bitwise equal.  At n = 7
-// the same change cost occupancy (170 VGPRs against 115, whose 17 spilled
-// SGPRs are cheap) and ran 121 us against 108 us; 2-row bands were slower at
-// both widths.
+// Weights of the 4-row direct form come from LDS for n = 9 (see
+// direct_tree_lds): 148 us against 169 us per 3x4096x4096 FP32 image, bitwise
+// equal.  At n = 7 the same change cost occupancy (170 VGPRs against 115, whose
+// 17 spilled SGPRs are cheap) and ran 121 us against 108 us; 2-row bands were
+// slower at both widths.  FP32 at n >= 7 now takes the walking band below; the
+// 4-row form serves the 16-bit types.
 template <int R, int MODE> constexpr bool direct_lds() { return MODE == MODE_DIRECT25 && R >= 4; }
+
+// ---- walking band of the direct form (FP32, n >= 7) --------------------------------
+// One wave walks down a band of TH output rows, one row per step.  The n input
+// rows of the window and kWalkAhead rows in flight live in a ring of
+// Q = n + kWalkAhead slots: once output row j is stored, the slot of input row
+// j (its last reader) takes the load of row j + Q, which is first read
+// kWalkAhead steps later.  Each input row is loaded and its halos moved across
+// lanes once per band rather than once per 4-row band, and only the window and
+// the rows in flight are live (n = 7: 124 VGPRs, 4 waves per SIMD; n = 9: 168,
+// 3 waves; the 4-row form needed 115 VGPRs with 17 spilled SGPRs, and 213).
+// The weights come from LDS, each leaf reading its n just before its chains.
+// Every output is the same pairwise sum of n row chains as direct_tree, in the
+// same order, so the results are bitwise those of the 4-row band form.
+constexpr int kWalkAhead = 2;  // ring slots beyond the window
+constexpr int kWalkLdsR = 3;   // walking bands read their weights from LDS from this radius on
+template <class D, int R, int MODE> constexpr bool walk_n() {
+    return MODE == MODE_DIRECT25 && D::ESZ == 4 && R >= 3;
+}
+// whether the kernel copies the n x n weights to LDS
+template <class D, int R, int MODE> constexpr bool weights_lds() {
+    return walk_n<D, R, MODE>() ? R >= kWalkLdsR : direct_lds<R, MODE>();
+}
+
+// The pairwise sum over kernel rows LO..HI-1 of one output row; leaf(a, s)
+// writes row a's chain for the lane's VEC outputs.
+template <int LO, int HI, int VEC, class Leaf>
+__device__ __forceinline__ void walk_tree(const Leaf &leaf, float (&s)[VEC]) {
+    if constexpr (HI - LO == 1) {
+        leaf(std::integral_constant<int, LO>{}, s);
+    } else {
+        constexpr int n = HI - LO;
+        constexpr int half = n >= 8 ? (n > 8 ? 8 : 4) : (n > 4 ? 4 : (n > 2 ? 2 : 1));
+        float r[VEC];
+        walk_tree<LO, LO + half, VEC>(leaf, s);
+        walk_tree<LO + half, HI, VEC>(leaf, r);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s[e] = s[e] + r[e];
+    }
+}
+
+// f(integral_constant<J>) for J = LO, LO+1, ... < HI while f returns true.
+template <int LO, int HI, class F> __device__ __forceinline__ void each_step(const F &f) {
+    if constexpr (LO < HI) {
+        if (f(std::integral_constant<int, LO>{})) each_step<LO + 1, HI>(f);
+    }
+}
+
+template <class D, bool AL, int R, bool EDGE, int TH, int SAUX>
+__device__ __forceinline__ void band_walk(const ImgDev &im, const TapsN &tp, const float *Kl,
+                                          int plane, int xs, int y0, int y1, int lane) {
+    constexpr int VEC = D::VEC;
+    constexpr int NT_ = 2 * R + 1;
+    constexpr int Q = NT_ + kWalkAhead;
+    constexpr int WN = VEC + 2 * R;
+    constexpr bool KLDS = weights_lds<D, R, MODE_DIRECT25>();
+    const int H = im.rows, W = im.cols;
+    const int x = xs + lane * VEC;
+    bool cm[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) cm[e] = (x + e >= R) && (x + e < W - R);
+    const char *sbase = (const char *)im.in + (int64_t)plane * im.pstride * D::ESZ;
+    const int64_t sstride = im.pitch * D::ESZ;
+    const uint32_t sbytes = (uint32_t)W * D::ESZ;
+    char *dbase = (char *)im.out + (int64_t)plane * im.pstride * D::ESZ;
+    const int hoff = halo_offset_n<D, R>(xs, W, lane);
+    const int nrows = y1 - y0;
+    const int last = nrows - 1 + 2 * R;  // last window row of the band, counted from y0 - R
+    // rows past the band's last window row are issued with an empty buffer
+    // range (no memory access) rather than skipped: a load under a branch makes
+    // the compiler's wait counts assume the shorter path and wait for the load
+    // issued one step earlier, which removes the prefetch
+    const auto issue_row = [&](RawN<D, AL, R> &r, int i) {
+        const bool need = i <= last;
+        issue_n<D, R>(r, sbase + (int64_t)clampi(y0 - R + i, 0, H - 1) * sstride, need ? sbytes : 0u,
+                      x, hoff);
+    };
+
+    RawN<D, AL, R> raw[Q];
+    float win[Q][WN];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) issue_row(raw[i], i);
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) decode_n<D, R>(raw[i], win[i]);
+
+    // the LDS weight reads are ordered leaf by leaf through an opaque address
+    // (see direct_tree_lds); it is kept in one register for the whole band
+    float dep = 0.0f;
+    [[maybe_unused]] uint32_t kaddr = 0;
+    if constexpr (KLDS) kaddr = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl;
+    // one output row; u = j mod Q, known at compile time, names the ring slots
+    const auto step = [&](auto U, int j) {
+        constexpr int u = decltype(U)::value;
+        if (j >= nrows) return false;
+        decode_n<D, R>(raw[(u + 2 * R) % Q], win[(u + 2 * R) % Q]);
+        float o[VEC];
+        const auto leaf = [&](auto A, float (&s)[VEC]) {
+            constexpr int a = decltype(A)::value;
+            const float(&w)[WN] = win[(u + a) % Q];
+            float k[NT_];
+            if constexpr (KLDS) {
+                asm volatile("" : "+v"(kaddr) : "v"(dep));
+                const __attribute__((address_space(3))) float *Ka =
+                    (const __attribute__((address_space(3))) float *)(uintptr_t)kaddr;
+#pragma unroll
+                for (int b = 0; b < NT_; ++b) k[b] = Ka[a * NT_ + b];
+            } else {
+#pragma unroll
+                for (int b = 0; b < NT_; ++b) k[b] = tp.K[a * NT_ + b];
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) s[e] = w[e] * k[0];
+#pragma unroll
+            for (int b = 1; b < NT_; ++b)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s[e] = __builtin_fmaf(w[e + b], k[b], s[e]);
+            if constexpr (KLDS) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(s[e]), "+v"(dep));
+            }
+        };
+        walk_tree<0, NT_, VEC>(leaf, o);
+        const int y = y0 + j;
+        if constexpr (EDGE) {
+            const bool vr = (y >= R) && (y < H - R);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) o[e] = (vr && cm[e]) ? o[e] : 0.0f;
+        }
+        store_out<D, AL, SAUX>(dbase + (int64_t)y * sstride, sbytes, x, o);
+        issue_row(raw[u], j + Q);
+        return true;
+    };
+    // every step expanded at compile time: a loop this large is not unrolled, and
+    // a loop over ring periods kept copies of the ring at its back edge
+    each_step<0, TH>([&](auto J) {
+        return step(std::integral_constant<int, decltype(J)::value % Q>{}, decltype(J)::value);
+    });
+}
 
 // ---- one band ---------------------------------------------------------------------
 // MODE: MODE_FUSED (separable, register window), MODE_DIRECT25 (direct n x n
@@ -384,10 +523,16 @@ __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, co
     const int y1 = min(y0 + TH, im.rows);
     const bool col_edge = xs < R || xs + WAVE * D::VEC > im.cols - R;
     const bool row_edge = MODE != MODE_ROWPASS && (y0 < R || y0 + TH > im.rows - R);
-    if (col_edge || row_edge)
+    if constexpr (walk_n<D, R, MODE>()) {
+        if (col_edge || row_edge)
+            band_walk<D, AL, R, true, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
+        else
+            band_walk<D, AL, R, false, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
+    } else if (col_edge || row_edge) {
         band_n<D, AL, R, MODE, true, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
-    else
+    } else {
         band_n<D, AL, R, MODE, false, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
+    }
 }
 
 // One workgroup per logical tile (grids above 2^20 workgroups loop); with
@@ -398,7 +543,7 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, in
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const float *Kl = nullptr;
-    if constexpr (direct_lds<R, MODE>()) {
+    if constexpr (weights_lds<D, R, MODE>()) {
         constexpr int NK = (2 * R + 1) * (2 * R + 1);
         __shared__ float sK[NK];
         for (int i = threadIdx.x; i < NK; i += WAVE * WAVES) sK[i] = tp.K[i];
@@ -421,13 +566,15 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, in
 template <class D> struct GeomN {
     static constexpr int WAVES = waves_n(D::ESZ == 4 ? 0 : 1);
     static constexpr int TH_SEP = kThSepN;
-    static constexpr int TH_DIRECT = kThDirectN;
 };
 
 template <class D, bool AL, int R, int MODE>
 hipError_t launch_n_m(const ImgDev &im, const TapsN &tp, int64_t nblocks, hipStream_t s) {
     constexpr int W = GeomN<D>::WAVES;
-    constexpr int TH = MODE == MODE_DIRECT25 ? GeomN<D>::TH_DIRECT : GeomN<D>::TH_SEP;
+    constexpr int TH = MODE == MODE_DIRECT25 ? th_direct_n(D::ESZ == 4, R)
+                                             : GeomN<D>::TH_SEP;
+    static_assert(walk_n<D, R, MODE>() == (MODE == MODE_DIRECT25 && TH == kThWalkN && R >= 3),
+                  "the host's band height must match the kernel form");
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     // keep_out (the copy-back scratch): cached output stores in kernels of
     // their own

@@ -137,6 +137,23 @@ def test_full_kernel_signed(n):
     print(f"n={n}: max err / magnitude bound = {float(np.max(err[nz] / mag[nz])):.3e}")
 
 
+@pytest.mark.parametrize("n", (7, 9))
+@pytest.mark.parametrize("rows", (7, 9, 15, 16, 17, 19, 20, 31, 33, 48))
+def test_full_kernel_band_heights(n, rows):
+    """FP32 direct n x n at n >= 7 walks 16-row bands with a ring of input
+    rows: heights around the band and ring lengths, one and several strips
+    (ragged), against the oracle's bound and the zero frame."""
+    for P, C in ((2, 197), (1, 600)):
+        host = (synth.image(1300 + rows, P, rows, C) * 2 - 1).astype(np.float32)
+        K = synth.kernel_signed(1400 + n, n)
+        got = gu.to_host_bits(run_n("full", gu.to_device(host), K)).astype(np.float64)
+        ref = oracle_full(host, K)
+        mag = oracle.conv_direct_n(np.abs(host.astype(np.float64)),
+                                   np.abs(K.astype(np.float64)), nthreads=0)
+        assert np.all(np.abs(got - ref) <= (n + 5) * gu.U32 * mag), (P, rows, C)
+        assert border_zero_n(got, n), (P, rows, C)
+
+
 @pytest.mark.parametrize("n", (3, 7, 9))
 def test_full_kernel_shift_and_impulse_exact(n):
     """K with a single 1 moves the image (exact); an impulse reproduces K
@@ -220,7 +237,7 @@ def test_16bit_widths(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("n", (3, 9))
+@pytest.mark.parametrize("n", (3, 7, 9))
 def test_unaligned_matches_aligned(dtype, n):
     """Offset base and odd pitch run the element-wise path: same bits."""
     torch = _torch()
@@ -242,7 +259,7 @@ def test_unaligned_matches_aligned(dtype, n):
         assert np.array_equal(gu.to_host_bits(v_out), ref), f
 
 
-@pytest.mark.parametrize("n", (3, 9))
+@pytest.mark.parametrize("n", (3, 7, 9))
 def test_copy_back_in_place(n):
     torch = _torch()
     P, R, C = 3, 50, 400
