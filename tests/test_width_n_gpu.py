@@ -275,20 +275,22 @@ def test_copy_back_in_place(n):
         assert torch.equal(b, ref), f
 
 
-def test_full_size_sampled_rows_width9():
-    """3 x 4096 x 4096 FP32 at n = 9: sampled rows of the fused form and of a
-    full signed kernel against the oracle on row crops; fused == 2pass."""
+@pytest.mark.parametrize("n", (7, 9))
+def test_full_size_sampled_rows(n):
+    """3 x 4096 x 4096 FP32 at n = 7, 9 (the size the benchmark times): sampled
+    rows of the fused form and of a full signed kernel (walking bands: rows at
+    band starts and ends) against the oracle on row crops; fused == 2pass."""
     torch = _torch()
-    P, R, C, n = 3, 4096, 4096, 9
+    P, R, C = 3, 4096, 4096
     r = n // 2
-    host = synth.image(1200, P, R, C)
-    k = synth.taps_random_n(1201, n)
-    K = synth.kernel_signed(1202, n)
+    host = synth.image(1200 + n, P, R, C)
+    k = synth.taps_random_n(1201 + n, n)
+    K = synth.kernel_signed(1202 + n, n)
     a = gu.to_device(host)
     fused = run_n("fused", a, k)
     assert torch.equal(fused, run_n("2pass", a, k))
     full = run_n("full", a, K)
-    rows = [0, 3, 4, 5, 7, 8, 9, 1023, 2048, 4090, 4091, 4092, 4095]
+    rows = [0, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 1023, 2047, 2048, 4079, 4080, 4090, 4091, 4092, 4095]
     for y in rows:
         if y < r or y >= R - r:
             assert torch.all(fused[:, y, :] == 0) and torch.all(full[:, y, :] == 0)
