@@ -94,10 +94,8 @@ struct TapsN {
 constexpr int kMaxWidthN = 9;
 constexpr int kThSepN = 8;     // rows per band: fused, row and column kernels
 constexpr int kThDirectN = 4;  // rows per band: direct n x n
-constexpr int kThWalkN = 16;   // rows per band: direct n x n, FP32, n >= 7 (walking bands)
-constexpr int th_direct_n(bool f32, int radius) {
-    return f32 && radius >= 3 ? kThWalkN : kThDirectN;
-}
+constexpr int kThWalkN = 16;   // rows per band: direct n x n, n >= 7 (walking bands)
+constexpr int th_direct_n(int radius) { return radius >= 3 ? kThWalkN : kThDirectN; }
 constexpr int waves_n(int) { return 1; }
 constexpr int kXcdChunkRowsN = 64;  // rows per XCD chunk of the width-n kernels
 

@@ -9,7 +9,7 @@
 // buffer load per lane per row, R-column halos from neighbouring lanes by DPP,
 // per-row buffer resources so that lanes past the edge read 0 and drop their
 // stores.  Every band is fully unrolled: all TH+2R input rows are issued
-// first; a short last band computes TH rows and stores only its own (the FP32
+// first; a short last band computes TH rows and stores only its own (the
 // direct form at n >= 7 walks 16-row bands instead, loading rows as it goes).
 // The output frame of R pixels is written as +0.0.
 //
@@ -179,104 +179,32 @@ __device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], 
     }
 }
 
-// The same tree for n = 9 with two changes that leave every operation and its
-// order as above: leaf a reads its n weights from LDS just before its chains
-// (81 weights next to the descriptor do not fit the scalar registers, and
-// parking them in vector lanes cost one read-back per ~8 multiply-adds), and
-// the window rows are decoded when first needed (row i at leaf i-TH+1), so
-// that only about TH decoded rows are live instead of TH+2R.  Scheduling
-// barriers do not hold pure arithmetic in place, so each leaf's results pass
-// through empty asm statements chained on a token, and the next leaf's weight
-// address and raw row through one that consumes the token: no value changes,
-// but nothing of leaf a can be hoisted above the end of leaf a-1.
-template <class D, int R>
-__device__ __forceinline__ void after(RawN<D, true, R> &r, float dep) {
-    asm volatile("" : "+v"(r.m) : "v"(dep));
-#pragma unroll
-    for (int j = 0; j < (int)(sizeof(r.h) / sizeof(r.h[0])); ++j) asm volatile("" : "+v"(r.h[j]) : "v"(dep));
-}
-template <class D, int R>
-__device__ __forceinline__ void after(RawN<D, false, R> &r, float dep) {
-#pragma unroll
-    for (int e = 0; e < D::VEC + 2 * R; ++e) asm volatile("" : "+v"(r.e[e]) : "v"(dep));
-}
 
-template <int LO, int HI, int NT_, int TH, int VEC, int WN, class RawRow, class Dec>
-__device__ __forceinline__ void direct_tree_lds(RawRow (&raw)[TH + NT_ - 1],
-                                                float (&w)[TH + NT_ - 1][WN], const Dec &decode,
-                                                uint32_t kaddr, float &dep, float (&s)[TH][VEC]) {
-    if constexpr (HI - LO == 1) {
-        constexpr int a = LO;
-        if constexpr (a == 0) {
-#pragma unroll
-            for (int i = 0; i < TH - 1; ++i) decode(raw[i], w[i]);
-        }
-        after(raw[a + TH - 1], dep);
-        decode(raw[a + TH - 1], w[a + TH - 1]);
-        asm volatile("" : "+v"(kaddr) : "v"(dep));
-        const __attribute__((address_space(3))) float *Kl =
-            (const __attribute__((address_space(3))) float *)(uintptr_t)kaddr;
-        float k[NT_];
-#pragma unroll
-        for (int b = 0; b < NT_; ++b) k[b] = Kl[a * NT_ + b];
-#pragma unroll
-        for (int j = 0; j < TH; ++j)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) s[j][e] = w[j + a][e] * k[0];
-#pragma unroll
-        for (int b = 1; b < NT_; ++b) {
-#pragma unroll
-            for (int j = 0; j < TH; ++j)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) s[j][e] = __builtin_fmaf(w[j + a][e + b], k[b], s[j][e]);
-        }
-        // the token depends on every result of this leaf
-#pragma unroll
-        for (int j = 0; j < TH; ++j)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(s[j][e]), "+v"(dep));
-    } else {
-        constexpr int n = HI - LO;
-        constexpr int half = n >= 8 ? (n > 8 ? 8 : 4) : (n > 4 ? 4 : (n > 2 ? 2 : 1));
-        float r[TH][VEC];
-        direct_tree_lds<LO, LO + half, NT_, TH, VEC, WN>(raw, w, decode, kaddr, dep, s);
-        direct_tree_lds<LO + half, HI, NT_, TH, VEC, WN>(raw, w, decode, kaddr, dep, r);
-#pragma unroll
-        for (int j = 0; j < TH; ++j)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) s[j][e] = s[j][e] + r[j][e];
-    }
-}
-
-// Weights of the 4-row direct form come from LDS for n = 9 (see
-// direct_tree_lds): 148 us against 169 us per 3x4096x4096 FP32 image, bitwise
-// equal.  At n = 7 the same change cost occupancy (170 VGPRs against 115, whose
-// 17 spilled SGPRs are cheap) and ran 121 us against 108 us; 2-row bands were
-// slower at both widths.  FP32 at n >= 7 now takes the walking band below; the
-// 4-row form serves the 16-bit types.
-template <int R, int MODE> constexpr bool direct_lds() { return MODE == MODE_DIRECT25 && R >= 4; }
-
-// ---- walking band of the direct form (FP32, n >= 7) --------------------------------
+// ---- walking band of the direct form (n >= 7) --------------------------------------
 // One wave walks down a band of TH output rows, one row per step.  The n input
 // rows of the window and kWalkAhead rows in flight live in a ring of
 // Q = n + kWalkAhead slots: once output row j is stored, the slot of input row
 // j (its last reader) takes the load of row j + Q, which is first read
 // kWalkAhead steps later.  Each input row is loaded and its halos moved across
 // lanes once per band rather than once per 4-row band, and only the window and
-// the rows in flight are live (n = 7: 124 VGPRs, 4 waves per SIMD; n = 9: 168,
-// 3 waves; the 4-row form needed 115 VGPRs with 17 spilled SGPRs, and 213).
-// The weights come from LDS, each leaf reading its n just before its chains.
-// Every output is the same pairwise sum of n row chains as direct_tree, in the
-// same order, so the results are bitwise those of the 4-row band form.
+// the rows in flight are live (FP32: n = 7 124 VGPRs, 4 waves per SIMD; n = 9
+// 168, 3 waves; 16-bit storage, 8 values per lane: 165 / 217 VGPRs).  The
+// 4-row form loaded all its rows up front: FP32 n = 9 needed 213 VGPRs and
+// 16-bit n = 9 345 (one wave per SIMD).  The n x n weights do not fit the
+// scalar registers next to the addressing (the compiler parked them in vector
+// lanes and read them back, one read-back per ~8 multiply-adds), so each
+// workgroup copies them to LDS and each leaf of the pairwise sum reads its n
+// just before its chains.  Plain LDS reads were hoisted to the top of the band
+// (and pinned the weights in registers), and scheduling barriers do not hold
+// arithmetic in place, so each leaf's results pass through empty asm
+// statements chained on a token that the next leaf's weight address consumes:
+// no value changes, but nothing of leaf a+1 can move above leaf a.  Every
+// output is the same pairwise sum of n row chains as direct_tree, in the same
+// order, so the results are bitwise those of the 4-row band form.
 constexpr int kWalkAhead = 2;  // ring slots beyond the window
-constexpr int kWalkLdsR = 3;   // walking bands read their weights from LDS from this radius on
-template <class D, int R, int MODE> constexpr bool walk_n() {
-    return MODE == MODE_DIRECT25 && D::ESZ == 4 && R >= 3;
-}
+template <class D, int R, int MODE> constexpr bool walk_n() { return MODE == MODE_DIRECT25 && R >= 3; }
 // whether the kernel copies the n x n weights to LDS
-template <class D, int R, int MODE> constexpr bool weights_lds() {
-    return walk_n<D, R, MODE>() ? R >= kWalkLdsR : direct_lds<R, MODE>();
-}
+template <class D, int R, int MODE> constexpr bool weights_lds() { return walk_n<D, R, MODE>(); }
 
 // The pairwise sum over kernel rows LO..HI-1 of one output row; leaf(a, s)
 // writes row a's chain for the lane's VEC outputs.
@@ -339,8 +267,8 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const TapsN &tp, con
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) decode_n<D, R>(raw[i], win[i]);
 
-    // the LDS weight reads are ordered leaf by leaf through an opaque address
-    // (see direct_tree_lds); it is kept in one register for the whole band
+    // the LDS weight reads are ordered leaf by leaf through an opaque address,
+    // kept in one register for the whole band
     float dep = 0.0f;
     [[maybe_unused]] uint32_t kaddr = 0;
     if constexpr (KLDS) kaddr = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl;
@@ -461,13 +389,6 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, const 
         }
         float w[TH + 2 * R][WN];
         float dsum[DIRECT ? TH : 1][VEC];
-        if constexpr (direct_lds<R, MODE>()) {
-            const auto dec_row = [](const RawIn &r, float (&v)[WN]) { decode_n<D, R>(r, v); };
-            float dep = 0.0f;
-            direct_tree_lds<0, NT_, NT_, TH, VEC, WN>(
-                raw, w, dec_row, (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl,
-                dep, dsum);
-        } else {
 #pragma unroll
         for (int i = 0; i < TH + 2 * R; ++i) {
             if constexpr (COL) {
@@ -482,7 +403,6 @@ __device__ __forceinline__ void band_n(const ImgDev &im, const TapsN &tp, const 
             }
         }
         if constexpr (DIRECT) direct_tree<0, NT_, NT_, TH, VEC, WN>(w, tp.K, dsum);
-        }
 #pragma unroll
         for (int j = 0; j < TH; ++j) {
             const int y = y0 + j;
@@ -571,7 +491,7 @@ template <class D> struct GeomN {
 template <class D, bool AL, int R, int MODE>
 hipError_t launch_n_m(const ImgDev &im, const TapsN &tp, int64_t nblocks, hipStream_t s) {
     constexpr int W = GeomN<D>::WAVES;
-    constexpr int TH = MODE == MODE_DIRECT25 ? th_direct_n(D::ESZ == 4, R)
+    constexpr int TH = MODE == MODE_DIRECT25 ? th_direct_n(R)
                                              : GeomN<D>::TH_SEP;
     static_assert(walk_n<D, R, MODE>() == (MODE == MODE_DIRECT25 && TH == kThWalkN && R >= 3),
                   "the host's band height must match the kernel form");
