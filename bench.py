@@ -303,7 +303,8 @@ def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
     """Width-n forms on the 3x4096x4096 FP32 image: time per launch, MPix/s and
     both rooflines.  flops per plane-pixel: an n-tap filter is 1 multiply and
     n-1 FMAs (2n-1 flops); fused / two-pass run two of them, the direct forms n
-    row chains plus n-1 adds (2n^2-1)."""
+    row chains plus n-1 adds (2n^2-1).  The full n x n kernel at n = 7, 9 is
+    also timed on the same image in FP16 storage."""
     dev = torch.device("cuda:0")
     base = torch.from_numpy(host).to(dev)
     S = max(1, args.sets)
@@ -343,7 +344,27 @@ def bench_widths(torch, cs, synth, host, args, widths=(1, 3, 5, 7, 9)):
             }
         res[f"n{n}"] = row
     del ins, outs, tmp
-    return {"alu_peak_tflops": ALU_PEAK_TFLOPS, "steps": steps, "results": res}
+    # the direct n x n forms on FP16 storage (4 B per plane-pixel), n = 7, 9
+    ins16 = [base.half()] + [base.half() for _ in range(S - 1)]
+    outs16 = [torch.empty_like(ins16[0]) for _ in range(S)]
+    img16 = cs.image_of(ins16[0])
+    p16 = ctypes.byref(img16)
+    pin16 = [ctypes.c_void_p(t.data_ptr()) for t in ins16]
+    pout16 = [ctypes.c_void_p(t.data_ptr()) for t in outs16]
+    res16 = {}
+    for n in (7, 9):
+        K = synth.kernel_signed(3 + n, n)
+        KK = (ctypes.c_float * (n * n))(*[float(v) for v in K.reshape(-1)])
+        fn = lambda i: check(cs, L.conv_2d_direct(pin16[i % S], pout16[i % S], KK, n, p16, hs))  # noqa: E731
+        avg = timed(torch, fn, steps, max(3, args.warmup // 2)) / steps
+        res16[f"n{n}"] = {"full": {
+            "ms_per_step": avg,
+            "mpix_per_s": (R * C) / (avg * 1e-3) / 1e6,
+            "frac_of_hbm_peak": 4 * P * R * C / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "frac_of_alu_peak": (2 * n * n - 1) * P * R * C / (avg * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+        }}
+    del ins16, outs16
+    return {"alu_peak_tflops": ALU_PEAK_TFLOPS, "steps": steps, "results": res, "f16_results": res16}
 
 
 def bench_hwc(torch, cs, host, k, args):
