@@ -92,13 +92,18 @@ def parse():
     return ap.parse_args()
 
 
+# the sources the width-5 kernels (whose traffic profiles/traffic.json records)
+# are compiled from
+TRAFFIC_SOURCES = ("conv_internal.h", "conv_kernels.h", "conv_kernels_bf16.hip", "conv_kernels_f16.hip",
+                   "conv_kernels_f32.hip")
+
+
 def kernel_src_sha() -> str:
-    """sha256 over the device-code sources (conv_kernels*.{h,hip}, conv_internal.h)."""
+    """sha256 over the sources of the width-5 kernels (TRAFFIC_SOURCES)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(KERNEL_DIR)):
-        if name.startswith("conv_kernels") or name == "conv_internal.h":
-            with open(os.path.join(KERNEL_DIR, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(KERNEL_DIR, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
