@@ -202,9 +202,8 @@ __device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], 
 // output is the same pairwise sum of n row chains as direct_tree, in the same
 // order, so the results are bitwise those of the 4-row band form.
 constexpr int kWalkAhead = 2;  // ring slots beyond the window
+// the walking form, which also is the one that reads its weights from LDS
 template <class D, int R, int MODE> constexpr bool walk_n() { return MODE == MODE_DIRECT25 && R >= 3; }
-// whether the kernel copies the n x n weights to LDS
-template <class D, int R, int MODE> constexpr bool weights_lds() { return walk_n<D, R, MODE>(); }
 
 // The pairwise sum over kernel rows LO..HI-1 of one output row; leaf(a, s)
 // writes row a's chain for the lane's VEC outputs.
@@ -231,13 +230,12 @@ template <int LO, int HI, class F> __device__ __forceinline__ void each_step(con
 }
 
 template <class D, bool AL, int R, bool EDGE, int TH, int SAUX>
-__device__ __forceinline__ void band_walk(const ImgDev &im, const TapsN &tp, const float *Kl,
-                                          int plane, int xs, int y0, int y1, int lane) {
+__device__ __forceinline__ void band_walk(const ImgDev &im, const float *Kl, int plane, int xs, int y0,
+                                          int y1, int lane) {
     constexpr int VEC = D::VEC;
     constexpr int NT_ = 2 * R + 1;
     constexpr int Q = NT_ + kWalkAhead;
     constexpr int WN = VEC + 2 * R;
-    constexpr bool KLDS = weights_lds<D, R, MODE_DIRECT25>();
     const int H = im.rows, W = im.cols;
     const int x = xs + lane * VEC;
     bool cm[VEC];
@@ -270,8 +268,7 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const TapsN &tp, con
     // the LDS weight reads are ordered leaf by leaf through an opaque address,
     // kept in one register for the whole band
     float dep = 0.0f;
-    [[maybe_unused]] uint32_t kaddr = 0;
-    if constexpr (KLDS) kaddr = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl;
+    uint32_t kaddr = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)Kl;
     // one output row; u = j mod Q, known at compile time, names the ring slots
     const auto step = [&](auto U, int j) {
         constexpr int u = decltype(U)::value;
@@ -282,26 +279,19 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const TapsN &tp, con
             constexpr int a = decltype(A)::value;
             const float(&w)[WN] = win[(u + a) % Q];
             float k[NT_];
-            if constexpr (KLDS) {
-                asm volatile("" : "+v"(kaddr) : "v"(dep));
-                const __attribute__((address_space(3))) float *Ka =
-                    (const __attribute__((address_space(3))) float *)(uintptr_t)kaddr;
+            asm volatile("" : "+v"(kaddr) : "v"(dep));
+            const __attribute__((address_space(3))) float *Ka =
+                (const __attribute__((address_space(3))) float *)(uintptr_t)kaddr;
 #pragma unroll
-                for (int b = 0; b < NT_; ++b) k[b] = Ka[a * NT_ + b];
-            } else {
-#pragma unroll
-                for (int b = 0; b < NT_; ++b) k[b] = tp.K[a * NT_ + b];
-            }
+            for (int b = 0; b < NT_; ++b) k[b] = Ka[a * NT_ + b];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) s[e] = w[e] * k[0];
 #pragma unroll
             for (int b = 1; b < NT_; ++b)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) s[e] = __builtin_fmaf(w[e + b], k[b], s[e]);
-            if constexpr (KLDS) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(s[e]), "+v"(dep));
-            }
+            for (int e = 0; e < VEC; ++e) asm volatile("" : "+v"(s[e]), "+v"(dep));
         };
         walk_tree<0, NT_, VEC>(leaf, o);
         const int y = y0 + j;
@@ -445,9 +435,9 @@ __device__ __forceinline__ void run_tile_n(const ImgDev &im, const TapsN &tp, co
     const bool row_edge = MODE != MODE_ROWPASS && (y0 < R || y0 + TH > im.rows - R);
     if constexpr (walk_n<D, R, MODE>()) {
         if (col_edge || row_edge)
-            band_walk<D, AL, R, true, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
+            band_walk<D, AL, R, true, TH, SAUX>(im, Kl, plane, xs, y0, y1, lane);
         else
-            band_walk<D, AL, R, false, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
+            band_walk<D, AL, R, false, TH, SAUX>(im, Kl, plane, xs, y0, y1, lane);
     } else if (col_edge || row_edge) {
         band_n<D, AL, R, MODE, true, TH, SAUX>(im, tp, Kl, plane, xs, y0, y1, lane);
     } else {
@@ -463,7 +453,7 @@ __global__ __launch_bounds__(WAVE *WAVES) void k_image_n(ImgDev im, TapsN tp, in
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const float *Kl = nullptr;
-    if constexpr (weights_lds<D, R, MODE>()) {
+    if constexpr (walk_n<D, R, MODE>()) {
         constexpr int NK = (2 * R + 1) * (2 * R + 1);
         __shared__ float sK[NK];
         for (int i = threadIdx.x; i < NK; i += WAVE * WAVES) sK[i] = tp.K[i];
