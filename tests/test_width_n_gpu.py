@@ -137,20 +137,27 @@ def test_full_kernel_signed(n):
     print(f"n={n}: max err / magnitude bound = {float(np.max(err[nz] / mag[nz])):.3e}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("n", (7, 9))
 @pytest.mark.parametrize("rows", (7, 9, 15, 16, 17, 19, 20, 31, 33, 48))
-def test_full_kernel_band_heights(n, rows):
-    """FP32 direct n x n at n >= 7 walks 16-row bands with a ring of input
+def test_full_kernel_band_heights(dtype, n, rows):
+    """The direct n x n form at n >= 7 walks 16-row bands with a ring of input
     rows: heights around the band and ring lengths, one and several strips
-    (ragged), against the oracle's bound and the zero frame."""
+    (ragged widths take the element-wise path), in every storage type, against
+    the oracle's bound (plus one rounding to 16 bits) and the zero frame."""
+    half_ulp = {"f32": 0.0, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}[dtype]
     for P, C in ((2, 197), (1, 600)):
-        host = (synth.image(1300 + rows, P, rows, C) * 2 - 1).astype(np.float32)
+        host32 = (synth.image(1300 + rows, P, rows, C) * 2 - 1).astype(np.float32)
+        bits = synth.to_storage(host32, dtype) if dtype != "f32" else host32
         K = synth.kernel_signed(1400 + n, n)
-        got = gu.to_host_bits(run_n("full", gu.to_device(host), K)).astype(np.float64)
-        ref = oracle_full(host, K)
-        mag = oracle.conv_direct_n(np.abs(host.astype(np.float64)),
+        got = oracle.decode(gu.to_host_bits(run_n("full", gu.to_device(bits, dtype), K)), dtype)
+        ref = oracle_full(bits, K, dtype)
+        mag = oracle.conv_direct_n(np.abs(oracle.decode(bits, dtype)),
                                    np.abs(K.astype(np.float64)), nthreads=0)
-        assert np.all(np.abs(got - ref) <= (n + 5) * gu.U32 * mag), (P, rows, C)
+        bound = (n + 5) * gu.U32 * mag * (1 + half_ulp) + half_ulp * np.abs(ref)
+        if dtype != "f32":
+            bound = bound + 2.0 ** -24
+        assert np.all(np.abs(got - ref) <= bound), (P, rows, C)
         assert border_zero_n(got, n), (P, rows, C)
 
 
