@@ -398,9 +398,11 @@ conv_status conv_tune_load(const char *path);
  * arrival order while a slot is free and their HBM footprint (input + output
  * bytes) fits the budget, packs the requests admitted together into one
  * launch on the next idle stream (the batch kernel; a lone request runs the
- * single-image kernel), and retires requests when the stream has written the
- * launch's token into its completion word (pinned host memory).  Requests that arrive while others run are admitted into
- * the next launch, on another stream, so their work overlaps on the device.
+ * single-image kernel), and retires requests when a one-lane kernel that the
+ * stream runs after the launch has written the launch's token into its
+ * completion word (pinned host memory).  Requests that arrive while others run
+ * are admitted into the next launch, on another stream, so their work overlaps
+ * on the device.
  * Each result is bitwise identical to a lone conv_sep5_1pass (fused) call.
  * The queue is host memory (request descriptors); the images stay in device
  * memory throughout.
