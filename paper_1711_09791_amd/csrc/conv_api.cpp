@@ -119,9 +119,10 @@ static std::mutex g_cfg_mu;
 // 64-image uneven batch): 8-row bands, one wave per workgroup, XCDs taking
 // turns on chunks of 8 band rows (batch: of 64 tiles), and for batches one
 // workgroup per tile.  The 16-bit direct 25-tap kernel, bound by its vector
-// ALU work, runs 16-row bands (the walking band form, which keeps five
-// decoded rows live): 50.0 / 48.2 us against 52.1 / 53.1 us with 8-row bands
-// for FP16 / BF16.  conv_tune re-derives them for a given workload.
+// ALU work, runs 16-row bands (a walking band): 50.0 / 48.2 us against
+// 52.1 / 53.1 us with 8-row bands for FP16 / BF16; on that geometry a single
+// image now runs the width-n walking band at n = 5 (47 / 43.5 us, bitwise the
+// same).  conv_tune re-derives them for a given workload.
 static conv_tile_cfg g_cfg[3][kKinds] = {
     {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}},
     {{8, 1, 0, 8, 0}, {8, 1, 0, 8, 0}, {16, 1, 0, 8, 0}},

@@ -25,7 +25,7 @@ conv_status check_width(int32_t n) {
 int64_t fill_desc_n(ImgDev *d, const void *in, void *out, float *tmp, const conv_image *img,
                     const Layout &L, bool direct, int radius) {
     conv_tile_cfg cfg{};
-    cfg.rows_per_tile = direct ? th_direct_n(radius) : kThSepN;
+    cfg.rows_per_tile = direct ? th_direct_n(img->dtype == CONV_F32, radius) : kThSepN;
     cfg.waves_per_wg = waves_n(img->dtype);
     cfg.xcd_slabs = kXcdChunkRowsN / cfg.rows_per_tile;
     return fill_desc(d, in, out, tmp, img, L, kNoTaps, cfg);

@@ -94,8 +94,12 @@ struct TapsN {
 constexpr int kMaxWidthN = 9;
 constexpr int kThSepN = 8;     // rows per band: fused, row and column kernels
 constexpr int kThDirectN = 4;  // rows per band: direct n x n
-constexpr int kThWalkN = 16;   // rows per band: direct n x n, n >= 7 (walking bands)
-constexpr int th_direct_n(int radius) { return radius >= 3 ? kThWalkN : kThDirectN; }
+constexpr int kThWalkN = 16;   // rows per band: direct n x n, walking bands
+// rows per band of the direct n x n form: walking bands from n = 7 on, and at
+// n = 5 for 16-bit storage (where the form is bound by the arithmetic)
+constexpr int th_direct_n(bool f32, int radius) {
+    return radius >= 3 || (radius == 2 && !f32) ? kThWalkN : kThDirectN;
+}
 constexpr int waves_n(int) { return 1; }
 constexpr int kXcdChunkRowsN = 64;  // rows per XCD chunk of the width-n kernels
 

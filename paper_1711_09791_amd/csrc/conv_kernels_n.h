@@ -202,8 +202,12 @@ __device__ __forceinline__ void direct_tree(const float (&w)[TH + NT_ - 1][WN], 
 // output is the same pairwise sum of n row chains as direct_tree, in the same
 // order, so the results are bitwise those of the 4-row band form.
 constexpr int kWalkAhead = 2;  // ring slots beyond the window
-// the walking form, which also is the one that reads its weights from LDS
-template <class D, int R, int MODE> constexpr bool walk_n() { return MODE == MODE_DIRECT25 && R >= 3; }
+// the walking form, which also is the one that reads its weights from LDS:
+// from n = 7 on, and at n = 5 in 16-bit storage (FP32 at n = 5 is bound by
+// memory, where the 4-row form, which issues all its rows at once, is faster)
+template <class D, int R, int MODE> constexpr bool walk_n() {
+    return MODE == MODE_DIRECT25 && (R >= 3 || (R == 2 && D::ESZ == 2));
+}
 
 // The pairwise sum over kernel rows LO..HI-1 of one output row; leaf(a, s)
 // writes row a's chain for the lane's VEC outputs.
@@ -481,9 +485,9 @@ template <class D> struct GeomN {
 template <class D, bool AL, int R, int MODE>
 hipError_t launch_n_m(const ImgDev &im, const TapsN &tp, int64_t nblocks, hipStream_t s) {
     constexpr int W = GeomN<D>::WAVES;
-    constexpr int TH = MODE == MODE_DIRECT25 ? th_direct_n(R)
+    constexpr int TH = MODE == MODE_DIRECT25 ? th_direct_n(D::ESZ == 4, R)
                                              : GeomN<D>::TH_SEP;
-    static_assert(walk_n<D, R, MODE>() == (MODE == MODE_DIRECT25 && TH == kThWalkN && R >= 3),
+    static_assert(walk_n<D, R, MODE>() == (MODE == MODE_DIRECT25 && TH == kThWalkN),
                   "the host's band height must match the kernel form");
     const int grid = (int)(nblocks < (1 << 20) ? nblocks : (1 << 20));
     // keep_out (the copy-back scratch): cached output stores in kernels of
@@ -527,6 +531,22 @@ hipError_t launch_image_n_t(const ImgDev &im, const TapsN &tp, int radius, int m
                             int64_t nblocks, hipStream_t s) {
     return im.aligned ? launch_n_a<D, true>(im, tp, radius, mode, nblocks, s)
                       : launch_n_a<D, false>(im, tp, radius, mode, nblocks, s);
+}
+
+// The width-5 direct 25-tap form in 16-bit storage, on its 16-row walking
+// geometry, runs the walking band above at n = 5: the same products K = k k^T
+// (rounded once on the host) and the same pairwise row sums, so the results are
+// bitwise those of the width-5 walking band, which it outruns (3x4096x4096:
+// FP16 50 -> 47 us, BF16 48 -> 43.5 us).  The descriptor is the width-5 one.
+template <class D>
+hipError_t launch_direct25_walk(const ImgDev &im, int64_t nblocks, hipStream_t s) {
+    static_assert(D::ESZ == 2 && walk_n<D, 2, MODE_DIRECT25>(), "16-bit storage walks at n = 5");
+    TapsN tp;
+    std::memset(&tp, 0, sizeof tp);
+    for (int i = 0; i < 5; ++i) tp.k[i] = im.tp.k[i];
+    for (int i = 0; i < 25; ++i) tp.K[i] = im.tp.K[i];
+    return im.aligned ? launch_n_m<D, true, 2, MODE_DIRECT25>(im, tp, nblocks, s)
+                      : launch_n_m<D, false, 2, MODE_DIRECT25>(im, tp, nblocks, s);
 }
 
 }  // namespace
