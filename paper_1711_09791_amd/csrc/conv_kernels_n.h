@@ -278,6 +278,13 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const float *Kl, int
         constexpr int u = decltype(U)::value;
         if (j >= nrows) return false;
         decode_n<D, R>(raw[(u + 2 * R) % Q], win[(u + 2 * R) % Q]);
+        if constexpr (std::is_same<D, F16>::value) {
+            // FP16 rows are kept as converted FP32 values: left to itself the
+            // compiler folds part of the conversions into mixed-precision FMAs,
+            // which ran this kernel 2-4% slower at n = 7 and 9 (same results)
+#pragma unroll
+            for (int e = 0; e < WN; ++e) asm volatile("" : "+v"(win[(u + 2 * R) % Q][e]));
+        }
         float o[VEC];
         const auto leaf = [&](auto A, float (&s)[VEC]) {
             constexpr int a = decltype(A)::value;
