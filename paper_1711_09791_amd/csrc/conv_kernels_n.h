@@ -98,8 +98,18 @@ __device__ __forceinline__ void issue_n(RawN<D, false, R> &r, const char *row, u
     }
 }
 
-// v[i] = A[x - R + i], i = 0 .. VEC+2R-1, as FP32.
-template <class D, int R>
+// Each decoded FP16 value as a value of its own: an empty asm statement keeps
+// the compiler from folding the conversion into mixed-precision FMAs (used by
+// the walking band, where those issued slower; no value changes).
+template <class D> __device__ __forceinline__ float dec_kept(uint32_t b) {
+    float f = dec(D{}, b);
+    if constexpr (std::is_same<D, F16>::value) asm volatile("" : "+v"(f));
+    return f;
+}
+
+// v[i] = A[x - R + i], i = 0 .. VEC+2R-1, as FP32; KEEP: FP16 values through
+// dec_kept.
+template <class D, int R, bool KEEP = false>
 __device__ __forceinline__ void decode_n(const RawN<D, true, R> &r, float (&v)[D::VEC + 2 * R]) {
     constexpr int HW = RawN<D, true, R>::HW;
     const uint32_t m[4] = {r.m.x, r.m.y, r.m.z, r.m.w};
@@ -120,14 +130,15 @@ __device__ __forceinline__ void decode_n(const RawN<D, true, R> &r, float (&v)[D
 #pragma unroll
         for (int i = 0; i < D::VEC + 2 * R; ++i) {
             const int j = i + SH;
-            v[i] = dec(D{}, (j & 1) ? (ext[j >> 1] >> 16) : ext[j >> 1]);
+            const uint32_t b = (j & 1) ? (ext[j >> 1] >> 16) : ext[j >> 1];
+            v[i] = KEEP ? dec_kept<D>(b) : dec(D{}, b);
         }
     }
 }
-template <class D, int R>
+template <class D, int R, bool KEEP = false>
 __device__ __forceinline__ void decode_n(const RawN<D, false, R> &r, float (&v)[D::VEC + 2 * R]) {
 #pragma unroll
-    for (int e = 0; e < D::VEC + 2 * R; ++e) v[e] = dec(D{}, r.e[e]);
+    for (int e = 0; e < D::VEC + 2 * R; ++e) v[e] = KEEP ? dec_kept<D>(r.e[e]) : dec(D{}, r.e[e]);
 }
 
 // ---- the arithmetic ---------------------------------------------------------------
@@ -267,7 +278,7 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const float *Kl, int
 #pragma unroll
     for (int i = 0; i < Q; ++i) issue_row(raw[i], i);
 #pragma unroll
-    for (int i = 0; i < 2 * R; ++i) decode_n<D, R>(raw[i], win[i]);
+    for (int i = 0; i < 2 * R; ++i) decode_n<D, R, true>(raw[i], win[i]);
 
     // the LDS weight reads are ordered leaf by leaf through an opaque address,
     // kept in one register for the whole band
@@ -277,14 +288,9 @@ __device__ __forceinline__ void band_walk(const ImgDev &im, const float *Kl, int
     const auto step = [&](auto U, int j) {
         constexpr int u = decltype(U)::value;
         if (j >= nrows) return false;
-        decode_n<D, R>(raw[(u + 2 * R) % Q], win[(u + 2 * R) % Q]);
-        if constexpr (std::is_same<D, F16>::value) {
-            // FP16 rows are kept as converted FP32 values: left to itself the
-            // compiler folds part of the conversions into mixed-precision FMAs,
-            // which ran this kernel 2-4% slower at n = 7 and 9 (same results)
-#pragma unroll
-            for (int e = 0; e < WN; ++e) asm volatile("" : "+v"(win[(u + 2 * R) % Q][e]));
-        }
+        // FP16 rows are kept as converted FP32 values (dec_kept): mixed-precision
+        // FMAs ran this kernel 2-4% slower at n = 5, 7 and 9 (same results)
+        decode_n<D, R, true>(raw[(u + 2 * R) % Q], win[(u + 2 * R) % Q]);
         float o[VEC];
         const auto leaf = [&](auto A, float (&s)[VEC]) {
             constexpr int a = decltype(A)::value;
